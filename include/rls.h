@@ -1,0 +1,222 @@
+/*
+ * rls.h -- batched lambda-sweep solver for regularized least squares on
+ * AMD Instinct MI355X (gfx950).
+ *
+ * The library solves, for every regularization parameter lambda_i of a sweep,
+ *
+ *     (A^T A + lambda_i^2 L^T D^2 L) x_i = A^T b                      (1)
+ *
+ * the normal equations of min ||A x - b||^2 + lambda^2 ||D L x||^2 (paper:
+ * Bolten, MacLachlan, Kilmer, "Multigrid preconditioning for regularized
+ * least-squares problems", Section 1 eqs. (LSreg), (ml) and Section 3.2 eq.
+ * (normal)).  L is the forward-difference gradient of Section 2 eq.
+ * (gradient), D a nonnegative diagonal weighting of its rows (Section 2,
+ * eq. (g) and the update D^(l) = diag(d^(l)) D^(l-1)).  All lambdas of a
+ * sweep run together on the GPU with preconditioned conjugate gradients; the
+ * preconditioner is one multigrid V-cycle (Algorithm 1) on a hierarchy that
+ * does not depend on lambda (Section 3.2), so it is built once per weighting
+ * and reused by every lambda.  Each solve returns x_i and the L-curve pair
+ * (||A x_i - b||_2, ||D L x_i||_2) of Section 1.
+ *
+ * Layout.  An image of nv x nh pixels is a vector of n = nv*nh values,
+ * pixel (i, j) at index i + nv*j (column-major, i vertical; Section 2).
+ * A batch of vectors is stored vector after vector.  The weights d cover the
+ * two gradient planes: d[i + nv*j] weights the vertical difference
+ * x(i+1,j) - x(i,j), d[n + i + nv*j] the horizontal difference
+ * x(i,j+1) - x(i,j).  With a Neumann gradient the last difference in each
+ * direction is identically zero and its weight is ignored; with a periodic
+ * gradient it wraps around.
+ *
+ * Memory.  "device" arguments are GPU pointers (for example torch tensor
+ * data_ptr() values) on the device current at rls_setup; "host" arguments are
+ * CPU pointers.  The caller owns every pointer it passes; the library copies
+ * what it keeps.  All device work is ordered on the caller's stream (a
+ * hipStream_t passed as void*, NULL for the null stream); every call returns
+ * after its results are in place (host outputs written, device outputs
+ * complete on that stream).
+ *
+ * Errors.  Calls never throw; they return an rls_status and leave a message
+ * for rls_last_error() (thread-local).  Per-lambda non-convergence or
+ * breakdown is reported in rls_solve_info.flags, not as a call failure.
+ */
+#ifndef RLS_H
+#define RLS_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef int rls_status;
+#define RLS_OK             0
+#define RLS_E_ARG         -1   /* invalid argument (sizes, values, nulls)   */
+#define RLS_E_HIP         -2   /* a HIP runtime call failed                 */
+#define RLS_E_OOM         -3   /* device allocation failed                  */
+#define RLS_E_NOT_SPD     -4   /* non-positive pivot in a coarsest solve    */
+#define RLS_E_UNSUPPORTED -5   /* valid but not supported configuration     */
+#define RLS_E_STATE       -6   /* call out of order / bad handle            */
+
+/* Forward operator kinds. */
+#define RLS_OP_BLUR_SEPARABLE 1  /* A = A_h (x) A_v, 1D convolutions        */
+#define RLS_OP_CSR            2  /* A general sparse m x n (tomography)      */
+
+/* Boundary conditions of a separable blur: (A_v x)_i = sum_k t_k x(i-k),
+ * k = -r..r, with x outside [0, n) taken from the periodic continuation,
+ * the half-sample symmetric reflection (x(-1) = x(0)), or zero. */
+#define RLS_BC_PERIODIC   0
+#define RLS_BC_REFLECTIVE 1
+#define RLS_BC_ZERO       2
+
+/* Gradient boundary (also selects the multigrid transfer boundary). */
+#define RLS_L_NEUMANN  0
+#define RLS_L_PERIODIC 1
+
+/* Arithmetic of the iteration. */
+#define RLS_PREC_FP64 0
+
+/* Tolerance semantics of rls_solve_sweep. */
+#define RLS_TOL_RELATIVE 0   /* ||A^T b - K x_i|| <= tol * ||A^T b||      */
+#define RLS_TOL_ABSOLUTE 1   /* ||A^T b - K x_i|| <= tol (paper Sec. 3.3) */
+
+/* Per-lambda result flags. */
+#define RLS_FLAG_CONVERGED 1
+#define RLS_FLAG_MAXIT     2
+#define RLS_FLAG_BREAKDOWN 4   /* p^T K p <= 0 or r^T z <= 0                */
+#define RLS_FLAG_NONFINITE 8
+
+typedef struct {
+    int kind;               /* RLS_OP_BLUR_SEPARABLE or RLS_OP_CSR           */
+    /* separable blur (paper Section 4.6: A is a Kronecker product of 1D
+     * Toeplitz-type matrices) */
+    int bc;                 /* RLS_BC_*                                      */
+    int r_v, r_h;           /* tap radii: 2r+1 taps per direction            */
+    const double* taps_v;   /* host, 2*r_v+1 values, t_{-r}..t_{r}           */
+    const double* taps_h;   /* host, 2*r_h+1 values                          */
+    /* general sparse (not supported by this build: RLS_E_UNSUPPORTED) */
+    int64_t m, nnz;
+    const int64_t* rowptr;  /* host, m+1 */
+    const int32_t* col;     /* host, nnz */
+    const float* val;       /* host, nnz */
+} rls_op_desc;
+
+typedef struct {
+    int nv, nh;             /* image size; both divisible by 2^(levels-1)    */
+    int lbc;                /* RLS_L_NEUMANN or RLS_L_PERIODIC               */
+    int levels;             /* multigrid levels >= 1; the coarsest level is
+                               solved exactly (Algorithm 1), at most 1024
+                               unknowns, every level at least 4 x 4          */
+    int nu;                 /* Chebyshev smoothing steps before and after the
+                               coarse correction (V(nu,nu)), 1..8            */
+    double cheb_ratio;      /* smoothing interval [rho/ratio, rho], rho the
+                               Gershgorin bound of diag(K_k)^-1 K_k; > 1     */
+    int precision;          /* RLS_PREC_FP64                                 */
+} rls_grid_desc;
+
+typedef struct {
+    int maxit;              /* PCG iteration cap per lambda (>= 1)           */
+    int tol_mode;           /* RLS_TOL_RELATIVE / RLS_TOL_ABSOLUTE           */
+    int poll_every;         /* host convergence check period, iterations     */
+} rls_sweep_opts;
+
+typedef struct {
+    int iters;              /* PCG iterations (products K p) taken           */
+    int flags;              /* RLS_FLAG_*                                    */
+    double relres;          /* recursive ||r|| / ||A^T b|| at exit           */
+    double relres_true;     /* ||A^T b - K x|| / ||A^T b|| recomputed        */
+} rls_solve_info;
+
+typedef struct rls_problem rls_problem;
+
+/* Build a problem: copy the operator description, construct the lambda-free
+ * multigrid hierarchy (separable Gram bands of A_k^T A_k = P^T A^T A P for
+ * the blur, paper Section 3.2 one-sided hierarchy) and install the weights.
+ * d: device, 2n values >= 0 and finite, or NULL for D = I (paper D^(0) = I).
+ * On success *out receives a handle to free with rls_destroy.
+ * Errors: RLS_E_ARG (bad sizes, radii >= n/2, non-finite taps, nu/levels out
+ * of range), RLS_E_UNSUPPORTED (sparse operator, precision), RLS_E_OOM,
+ * RLS_E_HIP. */
+rls_status rls_setup(rls_problem** out, const rls_op_desc* A,
+                     const rls_grid_desc* g, const double* d, void* stream);
+
+/* Install the weights of a new outer iteration l: rebuild the Galerkin
+ * coarse stencils of L^T D^2 L (paper Section 3.2: formed once per
+ * weighting, reused for every lambda).  d: device, 2n values (NULL: D = I).
+ * Errors: RLS_E_STATE (null handle), RLS_E_ARG (negative or non-finite
+ * weight), RLS_E_HIP. */
+rls_status rls_set_weights(rls_problem* p, const double* d, void* stream);
+
+/* Solve (1) for lam[0..nlam-1] at once.
+ * b:        device, n values (the data; A is square for the blur).
+ * lam:      host, nlam values > 0.
+ * tol:      > 0, see opts->tol_mode (NULL opts: relative, maxit 100000,
+ *           poll every 20 iterations).
+ * x0:       device, nlam*n initial guesses, or NULL for zero.
+ * x:        device, nlam*n solutions (may alias x0).
+ * resnorm:  host, nlam values ||A x_i - b||_2 (may be NULL).
+ * seminorm: host, nlam values ||D L x_i||_2 (may be NULL).
+ * info:     host, nlam records (may be NULL).
+ * Errors: RLS_E_ARG (nlam < 1, lam <= 0 or non-finite, tol <= 0, null
+ * b / x), RLS_E_NOT_SPD (coarsest matrix not positive definite),
+ * RLS_E_OOM, RLS_E_HIP. */
+rls_status rls_solve_sweep(rls_problem* p, const double* b, const double* lam,
+                           int nlam, double tol, const rls_sweep_opts* opts,
+                           const double* x0, double* x, double* resnorm,
+                           double* seminorm, rls_solve_info* info,
+                           void* stream);
+
+/* Free a handle (NULL is ignored). */
+void rls_destroy(rls_problem* p);
+
+/* Message of the last failed call on this thread ("" if none). */
+const char* rls_last_error(void);
+
+/* ---------------------------------------------------------------------
+ * Step-level entry points.  Each runs one step of the solver on its own,
+ * with the same kernels rls_solve_sweep uses, so that every step can be
+ * checked in isolation.  Level 0 is the finest grid.
+ * ------------------------------------------------------------------- */
+
+/* Grid size of a level. Errors: RLS_E_STATE, RLS_E_ARG (level range). */
+rls_status rls_level_shape(const rls_problem* p, int level, int* nv, int* nh);
+
+/* out_i = K_level(lam_i) v_i for i < nlam, K_level = P^T ... K ... P the
+ * Galerkin level operator (paper Section 3.2).  v, out: device,
+ * nlam * n_level values.  lam: host. */
+rls_status rls_apply_normal(rls_problem* p, int level, const double* lam,
+                            int nlam, const double* v, double* out,
+                            void* stream);
+
+/* z_i = V-cycle(lam_i) applied to r_i (Algorithm 1 with gamma = 1, the
+ * preconditioner of rls_solve_sweep).  r, z: device, nlam * n values. */
+rls_status rls_vcycle(rls_problem* p, const double* lam, int nlam,
+                      const double* r, double* z, void* stream);
+
+/* Copy the Galerkin stencil of L^T D^2 L on a level to the host: five
+ * planes of n_level values: centre, coupling to (i+1,j), to (i,j+1), to
+ * (i+1,j+1) and to (i-1,j+1) (the other four follow by symmetry). */
+rls_status rls_get_stencil(const rls_problem* p, int level, double* out);
+
+/* Copy one direction (0 vertical, 1 horizontal) of the separable Gram
+ * A_k^T A_k = G_h (x) G_v on a level to the host as a band: *bw receives
+ * the half bandwidth; out (host, may be NULL to query bw) receives
+ * n_dir * (2 bw + 1) values, row r, offset k in [-bw, bw] at
+ * out[r*(2bw+1) + k + bw] (coefficient of x(r+k), wrapped if periodic). */
+rls_status rls_get_gram_band(const rls_problem* p, int level, int dir,
+                             int* bw, double* out);
+
+/* Gershgorin bounds rho_k(lam_i) of diag(K_k)^-1 K_k used for the
+ * Chebyshev interval: rho (host) receives nlam values. */
+rls_status rls_gershgorin(rls_problem* p, int level, const double* lam,
+                          int nlam, double* rho, void* stream);
+
+/* y = A x (forward blur) or x = A^T y for nvec vectors (device). */
+rls_status rls_apply_forward(rls_problem* p, const double* x, double* y,
+                             int nvec, void* stream);
+rls_status rls_apply_adjoint(rls_problem* p, const double* y, double* x,
+                             int nvec, void* stream);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* RLS_H */

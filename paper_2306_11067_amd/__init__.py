@@ -1,0 +1,183 @@
+"""Batched multigrid-preconditioned lambda-sweep solver for regularized least
+squares on MI355X.
+
+Thin Python binding over librls.so (include/rls.h): it checks tensor
+dtypes/devices and passes raw pointers and torch's current HIP stream.  No
+arithmetic of the solver happens here and there is no CPU fallback: if the
+library is not built, every call raises.
+"""
+from __future__ import annotations
+
+import ctypes as C
+
+import numpy as np
+
+from . import _lib as L
+
+__all__ = ["Problem", "RLSError", "BC", "LBC"]
+
+BC = {"periodic": L.RLS_BC_PERIODIC, "reflective": L.RLS_BC_REFLECTIVE,
+      "zero": L.RLS_BC_ZERO}
+LBC = {"neumann": L.RLS_L_NEUMANN, "periodic": L.RLS_L_PERIODIC}
+
+
+class RLSError(RuntimeError):
+    def __init__(self, status: int, msg: str):
+        super().__init__(f"{L.STATUS_NAMES.get(status, status)}: {msg}")
+        self.status = status
+
+
+def _check(status: int):
+    if status != L.RLS_OK:
+        raise RLSError(status, L.load().rls_last_error().decode())
+
+
+def _dptr(t, name, numel=None):
+    import torch
+    if not isinstance(t, torch.Tensor):
+        raise TypeError(f"{name} must be a torch tensor")
+    if t.dtype != torch.float64 or not t.is_cuda or not t.is_contiguous():
+        raise TypeError(f"{name} must be a contiguous float64 CUDA tensor")
+    if numel is not None and t.numel() != numel:
+        raise ValueError(f"{name} must have {numel} elements, has {t.numel()}")
+    return C.c_void_p(t.data_ptr())
+
+
+def _stream():
+    import torch
+    return C.c_void_p(torch.cuda.current_stream().cuda_stream)
+
+
+def _dbl(a):
+    a = np.ascontiguousarray(a, dtype=np.float64)
+    return a, a.ctypes.data_as(C.POINTER(C.c_double))
+
+
+class Problem:
+    """One regularized least-squares problem (A, L, grid) on the GPU."""
+
+    def __init__(self, nv, nh, taps_v, taps_h, bc="reflective", lbc="neumann",
+                 levels=3, nu=2, cheb_ratio=4.0, weights=None):
+        self._lib = L.load()
+        self.nv, self.nh, self.levels = int(nv), int(nh), int(levels)
+        self.n = self.nv * self.nh
+        tv, ptv = _dbl(taps_v)
+        th, pth = _dbl(taps_h)
+        op = L.OpDesc()
+        op.kind = L.RLS_OP_BLUR_SEPARABLE
+        op.bc = BC[bc]
+        op.r_v = (len(tv) - 1) // 2
+        op.r_h = (len(th) - 1) // 2
+        op.taps_v, op.taps_h = ptv, pth
+        g = L.GridDesc(self.nv, self.nh, LBC[lbc], self.levels, int(nu),
+                       float(cheb_ratio), L.RLS_PREC_FP64)
+        h = C.c_void_p()
+        d = None if weights is None else _dptr(weights, "weights", 2 * self.n)
+        _check(self._lib.rls_setup(C.byref(h), C.byref(op), C.byref(g), d,
+                                   _stream()))
+        self._h = h
+
+    def close(self):
+        if getattr(self, "_h", None):
+            self._lib.rls_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    # ------------------------------------------------------------ main ABI
+    def set_weights(self, weights=None):
+        d = None if weights is None else _dptr(weights, "weights", 2 * self.n)
+        _check(self._lib.rls_set_weights(self._h, d, _stream()))
+
+    def solve_sweep(self, b, lams, tol, x0=None, x=None, maxit=100000,
+                    tol_mode="relative", poll_every=20):
+        import torch
+        lam, plam = _dbl(lams)
+        nl = len(lam)
+        if x is None:
+            x = torch.empty(nl * self.n, dtype=torch.float64, device=b.device)
+        opts = L.SweepOpts(int(maxit), L.RLS_TOL_ABSOLUTE if tol_mode ==
+                           "absolute" else L.RLS_TOL_RELATIVE, int(poll_every))
+        res = np.zeros(nl)
+        sem = np.zeros(nl)
+        info = (L.SolveInfo * nl)()
+        _check(self._lib.rls_solve_sweep(
+            self._h, _dptr(b, "b", self.n), plam, nl, float(tol),
+            C.byref(opts), None if x0 is None else _dptr(x0, "x0", nl * self.n),
+            _dptr(x, "x", nl * self.n),
+            res.ctypes.data_as(C.POINTER(C.c_double)),
+            sem.ctypes.data_as(C.POINTER(C.c_double)), info, _stream()))
+        inf = [dict(iters=i.iters, flags=i.flags, relres=i.relres,
+                    relres_true=i.relres_true) for i in info]
+        return x.view(nl, self.n), res, sem, inf
+
+    # ------------------------------------------------------------ step ABI
+    def level_shape(self, level):
+        a, b = C.c_int(), C.c_int()
+        _check(self._lib.rls_level_shape(self._h, level, C.byref(a), C.byref(b)))
+        return a.value, b.value
+
+    def apply_normal(self, level, lams, v):
+        import torch
+        lam, plam = _dbl(lams)
+        nv, nh = self.level_shape(level)
+        out = torch.empty(len(lam) * nv * nh, dtype=torch.float64,
+                          device=v.device)
+        _check(self._lib.rls_apply_normal(
+            self._h, level, plam, len(lam), _dptr(v, "v", len(lam) * nv * nh),
+            _dptr(out, "out"), _stream()))
+        return out
+
+    def vcycle(self, lams, r):
+        import torch
+        lam, plam = _dbl(lams)
+        z = torch.empty_like(r)
+        _check(self._lib.rls_vcycle(self._h, plam, len(lam),
+                                    _dptr(r, "r", len(lam) * self.n),
+                                    _dptr(z, "z"), _stream()))
+        return z
+
+    def stencil(self, level):
+        nv, nh = self.level_shape(level)
+        out = np.zeros(5 * nv * nh)
+        _check(self._lib.rls_get_stencil(
+            self._h, level, out.ctypes.data_as(C.POINTER(C.c_double))))
+        return out.reshape(5, nv * nh)
+
+    def gram_band(self, level, direction):
+        bw = C.c_int()
+        _check(self._lib.rls_get_gram_band(self._h, level, direction,
+                                           C.byref(bw), None))
+        nv, nh = self.level_shape(level)
+        n = nv if direction == 0 else nh
+        out = np.zeros(n * (2 * bw.value + 1))
+        _check(self._lib.rls_get_gram_band(
+            self._h, level, direction, C.byref(bw),
+            out.ctypes.data_as(C.POINTER(C.c_double))))
+        return out.reshape(n, 2 * bw.value + 1)
+
+    def gershgorin(self, level, lams):
+        lam, plam = _dbl(lams)
+        rho = np.zeros(len(lam))
+        _check(self._lib.rls_gershgorin(
+            self._h, level, plam, len(lam),
+            rho.ctypes.data_as(C.POINTER(C.c_double)), _stream()))
+        return rho
+
+    def forward(self, x, nvec=1):
+        import torch
+        y = torch.empty_like(x)
+        _check(self._lib.rls_apply_forward(self._h, _dptr(x, "x", nvec * self.n),
+                                           _dptr(y, "y"), nvec, _stream()))
+        return y
+
+    def adjoint(self, y, nvec=1):
+        import torch
+        x = torch.empty_like(y)
+        _check(self._lib.rls_apply_adjoint(self._h, _dptr(y, "y", nvec * self.n),
+                                           _dptr(x, "x"), nvec, _stream()))
+        return x

@@ -1,0 +1,793 @@
+// C-ABI of the library (include/rls.h): problem setup, weight updates and
+// the batched lambda sweep.  Host code here only allocates, validates and
+// sequences kernels; every arithmetic step runs on the GPU.
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <memory>
+#include <string>
+#include <vector>
+
+#include "rls_internal.h"
+
+using namespace rls;
+
+namespace {
+
+thread_local std::string g_last_error;
+
+rls_status fail(rls_status code, const std::string& msg) {
+    g_last_error = msg;
+    return code;
+}
+
+#define RLS_HIP(call)                                                        \
+    do {                                                                     \
+        hipError_t e_ = (call);                                              \
+        if (e_ != hipSuccess)                                                \
+            return fail(e_ == hipErrorOutOfMemory ? RLS_E_OOM : RLS_E_HIP,   \
+                        std::string(#call) + ": " + hipGetErrorString(e_)); \
+    } while (0)
+
+#define RLS_TRY(expr)                      \
+    do {                                   \
+        rls_status s_ = (expr);            \
+        if (s_ != RLS_OK) return s_;       \
+    } while (0)
+
+// A device allocation owned by the library.
+struct DBuf {
+    void* p = nullptr;
+    size_t bytes = 0;
+    DBuf() = default;
+    DBuf(const DBuf&) = delete;
+    DBuf& operator=(const DBuf&) = delete;
+    DBuf(DBuf&& o) noexcept : p(o.p), bytes(o.bytes) { o.p = nullptr; o.bytes = 0; }
+    DBuf& operator=(DBuf&& o) noexcept {
+        if (this != &o) { release(); p = o.p; bytes = o.bytes; o.p = nullptr; o.bytes = 0; }
+        return *this;
+    }
+    ~DBuf() { release(); }
+    void release() {
+        if (p) hipFree(p);
+        p = nullptr;
+        bytes = 0;
+    }
+    template <class T> T* as() const { return static_cast<T*>(p); }
+};
+
+rls_status dalloc(DBuf& b, size_t bytes) {
+    if (b.p && b.bytes >= bytes) return RLS_OK;
+    b.release();
+    if (bytes == 0) bytes = 8;
+    hipError_t e = hipMalloc(&b.p, bytes);
+    if (e != hipSuccess) {
+        b.p = nullptr;
+        return fail(e == hipErrorOutOfMemory ? RLS_E_OOM : RLS_E_HIP,
+                    std::string("hipMalloc: ") + hipGetErrorString(e));
+    }
+    b.bytes = bytes;
+    return RLS_OK;
+}
+
+struct Band {
+    int n = 0, bw = 0, map = MAP_ZERO, uniform = 0;
+    size_t taps_off = 0;     // offset (in doubles) of the uniform row in table
+    DBuf table, diag, rowabs;
+    BandDev dev() const {
+        BandDev b;
+        b.n = n;
+        b.bw = bw;
+        b.map = map;
+        b.uniform = uniform;
+        b.table = table.as<double>();
+        b.taps = table.as<double>() + taps_off;
+        b.diag = diag.as<double>();
+        b.rowabs = rowabs.as<double>();
+        return b;
+    }
+};
+
+struct Level {
+    int nv = 0, nh = 0;
+    Band gv, gh;
+    DBuf planes, srowabs;
+    int nine = 0;
+    int periodic = 0;
+    int64_t n() const { return (int64_t)nv * nh; }
+    LevelGeom geom() const {
+        LevelGeom g;
+        g.nv = nv;
+        g.nh = nh;
+        g.gv = gv.dev();
+        g.gh = gh.dev();
+        const double* pl = planes.as<double>();
+        const int64_t m = n();
+        g.S.c = pl;
+        g.S.cn = pl + m;
+        g.S.ce = pl + 2 * m;
+        g.S.cne = pl + 3 * m;
+        g.S.cse = pl + 4 * m;
+        g.S.rowabs = srowabs.as<double>();
+        g.S.nine = nine;
+        g.S.periodic = periodic;
+        return g;
+    }
+};
+
+// Per-sweep workspace, grown on demand.
+struct Work {
+    int cap = 0;                 // slots allocated
+    DBuf lam2, zero_lam2, st, active, beta, part, rho, cheb, kc, winv, info;
+    DBuf f;                      // A^T b (n)
+    DBuf r, z, p0, p1, q, y;     // fine vectors (cap * n)
+    std::vector<DBuf> lx, lxb, ld, lt, lf;   // per level (cap * n_k)
+};
+
+}  // namespace
+
+struct rls_problem {
+    int device = 0;
+    int nv = 0, nh = 0, levels = 0, nu = 2, bc = 0, lbc = 0;
+    double ratio = 4.0;
+    int periodic = 0;            // multigrid / gradient periodicity
+    int r_v = 0, r_h = 0;
+    std::vector<double> taps_v, taps_h;
+    std::vector<Level> lev;
+    Band av, ah, atv, ath;       // A and A^T bands (fine)
+    DBuf weights;                // 2n, or empty for D = I
+    int unit_weights = 1;
+    Work w;
+    int64_t n() const { return (int64_t)nv * nh; }
+};
+
+namespace {
+
+int max_part_slots(const rls_problem* P) {
+    int m = vec_blocks(P->n());
+    for (const Level& L : P->lev) m = std::max(m, apply_tiles(L.geom()));
+    return m;
+}
+
+rls_status check_launch(const char* where) {
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess)
+        return fail(RLS_E_HIP, std::string(where) + ": " + hipGetErrorString(e));
+    return RLS_OK;
+}
+
+rls_status ensure_work(rls_problem* P, int nslot) {
+    Work& w = P->w;
+    if (w.cap >= nslot) return RLS_OK;
+    const int cap = std::max(nslot, w.cap * 2);
+    const int64_t n = P->n();
+    const int L = P->levels;
+    RLS_TRY(dalloc(w.lam2, sizeof(double) * cap));
+    RLS_TRY(dalloc(w.zero_lam2, sizeof(double) * cap));
+    RLS_HIP(hipMemset(w.zero_lam2.p, 0, sizeof(double) * cap));
+    RLS_TRY(dalloc(w.st, sizeof(SlotState) * cap));
+    RLS_TRY(dalloc(w.active, sizeof(int) * cap));
+    RLS_TRY(dalloc(w.beta, sizeof(double) * cap));
+    RLS_TRY(dalloc(w.part, sizeof(double) * (size_t)cap * max_part_slots(P)));
+    RLS_TRY(dalloc(w.rho, sizeof(double) * (size_t)cap * L));
+    RLS_TRY(dalloc(w.cheb, sizeof(double) * (size_t)cap * L * 2 * P->nu));
+    const int64_t nc = P->lev.back().n();
+    RLS_TRY(dalloc(w.kc, sizeof(double) * (size_t)cap * nc * nc));
+    RLS_TRY(dalloc(w.winv, sizeof(double) * (size_t)cap * 2 * nc * nc));
+    RLS_TRY(dalloc(w.info, sizeof(int) * cap));
+    RLS_TRY(dalloc(w.f, sizeof(double) * n));
+    for (DBuf* b : {&w.r, &w.z, &w.p0, &w.p1, &w.q, &w.y})
+        RLS_TRY(dalloc(*b, sizeof(double) * (size_t)cap * n));
+    w.lx.resize(L);
+    w.lxb.resize(L);
+    w.ld.resize(L);
+    w.lt.resize(L);
+    w.lf.resize(L);
+    for (int k = 0; k < L; ++k) {
+        const size_t bytes = sizeof(double) * (size_t)cap * P->lev[k].n();
+        RLS_TRY(dalloc(w.lxb[k], bytes));
+        RLS_TRY(dalloc(w.ld[k], bytes));
+        RLS_TRY(dalloc(w.lt[k], bytes));
+        if (k > 0) {
+            RLS_TRY(dalloc(w.lx[k], bytes));
+            RLS_TRY(dalloc(w.lf[k], bytes));
+        }
+    }
+    w.cap = cap;
+    return RLS_OK;
+}
+
+// Build the 1D Gram band hierarchy of one direction.
+rls_status build_direction(rls_problem* P, const std::vector<double>& taps,
+                           int r, int dir, hipStream_t s) {
+    const int n0 = dir == 0 ? P->nv : P->nh;
+    const int blur_periodic = P->bc == RLS_BC_PERIODIC;
+    DBuf dtaps;
+    RLS_TRY(dalloc(dtaps, sizeof(double) * taps.size()));
+    RLS_HIP(hipMemcpyAsync(dtaps.p, taps.data(), sizeof(double) * taps.size(),
+                           hipMemcpyHostToDevice, s));
+    Band& A = dir == 0 ? P->av : P->ah;
+    Band& At = dir == 0 ? P->atv : P->ath;
+    A.n = At.n = n0;
+    A.bw = At.bw = r;
+    A.map = At.map = blur_periodic ? MAP_WRAP : MAP_ZERO;
+    A.uniform = At.uniform = 0;
+    RLS_TRY(dalloc(A.table, sizeof(double) * n0 * (2 * r + 1)));
+    RLS_TRY(dalloc(At.table, sizeof(double) * n0 * (2 * r + 1)));
+    for (Band* b : {&A, &At}) {
+        RLS_TRY(dalloc(b->diag, sizeof(double) * n0));
+        RLS_TRY(dalloc(b->rowabs, sizeof(double) * n0));
+    }
+    launch_blur_band(dtaps.as<double>(), r, n0, P->bc, A.table.as<double>(), s);
+    launch_transpose_band(A.table.as<double>(), n0, r, blur_periodic,
+                          At.table.as<double>(), s);
+    launch_band_stats(A.table.as<double>(), n0, r, A.diag.as<double>(),
+                      A.rowabs.as<double>(), s);
+    launch_band_stats(At.table.as<double>(), n0, r, At.diag.as<double>(),
+                      At.rowabs.as<double>(), s);
+    // level Gram bands
+    int bw = 2 * r;
+    for (int k = 0; k < P->levels; ++k) {
+        Level& L = P->lev[k];
+        Band& G = dir == 0 ? L.gv : L.gh;
+        const int nk = dir == 0 ? L.nv : L.nh;
+        G.n = nk;
+        G.bw = bw;
+        if (nk < 2 * bw + 1)
+            return fail(RLS_E_UNSUPPORTED,
+                        "level " + std::to_string(k) +
+                            " is narrower than its Gram band (" +
+                            std::to_string(nk) + " < " +
+                            std::to_string(2 * bw + 1) + "); use fewer levels "
+                            "or a smaller blur radius");
+        RLS_TRY(dalloc(G.table, sizeof(double) * nk * (2 * bw + 1)));
+        RLS_TRY(dalloc(G.diag, sizeof(double) * nk));
+        RLS_TRY(dalloc(G.rowabs, sizeof(double) * nk));
+        if (k == 0) {
+            launch_gram_band(A.table.as<double>(), nk, r, blur_periodic,
+                             G.table.as<double>(), bw, s);
+        } else {
+            Band& Gf = dir == 0 ? P->lev[k - 1].gv : P->lev[k - 1].gh;
+            launch_galerkin_band(Gf.table.as<double>(), Gf.n, Gf.bw,
+                                 P->periodic, G.table.as<double>(), bw, s);
+        }
+        launch_band_stats(G.table.as<double>(), nk, bw, G.diag.as<double>(),
+                          G.rowabs.as<double>(), s);
+        // Uniform fast path: periodic levels are circulant (every row equals
+        // row 0); the fine reflective Gram of a symmetric PSF equals the
+        // half-sample reflective convolution with its interior row.
+        G.taps_off = 0;
+        if (P->periodic) {
+            G.uniform = 1;
+            G.map = MAP_WRAP;
+        } else if (k == 0 && P->bc == RLS_BC_REFLECTIVE) {
+            bool sym = true;
+            for (int t = 0; t <= r; ++t)
+                if (taps[t] != taps[2 * r - t]) sym = false;
+            G.uniform = sym ? 1 : 0;
+            G.map = sym ? MAP_REFLECT : MAP_ZERO;
+            G.taps_off = sym ? (size_t)(nk / 2) * (2 * bw + 1) : 0;
+        } else {
+            G.uniform = 0;
+            G.map = MAP_ZERO;
+        }
+        bw = (bw + 2) / 2;
+    }
+    RLS_TRY(check_launch("build_direction"));
+    RLS_HIP(hipStreamSynchronize(s));   // dtaps goes out of scope
+    return RLS_OK;
+}
+
+rls_status install_weights(rls_problem* P, const double* d, hipStream_t s) {
+    const int64_t n = P->n();
+    if (d) {
+        // validate the caller's weights before replacing the current ones
+        DBuf bad;
+        RLS_TRY(dalloc(bad, sizeof(int)));
+        RLS_HIP(hipMemsetAsync(bad.p, 0, sizeof(int), s));
+        launch_check_weights(d, 2 * n, bad.as<int>(), s);
+        int hbad = 0;
+        RLS_HIP(hipMemcpyAsync(&hbad, bad.p, sizeof(int), hipMemcpyDeviceToHost,
+                               s));
+        RLS_HIP(hipStreamSynchronize(s));
+        if (hbad) return fail(RLS_E_ARG, "weights must be finite and >= 0");
+        RLS_TRY(dalloc(P->weights, sizeof(double) * 2 * n));
+        RLS_HIP(hipMemcpyAsync(P->weights.p, d, sizeof(double) * 2 * n,
+                               hipMemcpyDeviceToDevice, s));
+        P->unit_weights = 0;
+    } else {
+        P->weights.release();
+        P->unit_weights = 1;
+    }
+    for (int k = 0; k < P->levels; ++k) {
+        Level& L = P->lev[k];
+        const int64_t m = L.n();
+        RLS_TRY(dalloc(L.planes, sizeof(double) * 5 * m));
+        RLS_TRY(dalloc(L.srowabs, sizeof(double) * m));
+        L.periodic = P->periodic;
+        L.nine = k > 0;
+        if (k == 0)
+            launch_fine_stencil(P->unit_weights ? nullptr : P->weights.as<double>(),
+                                L.nv, L.nh, P->periodic, L.planes.as<double>(), s);
+        else
+            launch_galerkin_stencil(P->lev[k - 1].planes.as<double>(),
+                                    P->lev[k - 1].nv, P->lev[k - 1].nh,
+                                    P->periodic, L.planes.as<double>(), s);
+        launch_stencil_rowabs(L.planes.as<double>(), L.nv, L.nh, P->periodic,
+                              L.srowabs.as<double>(), s);
+    }
+    RLS_TRY(check_launch("install_weights"));
+    return RLS_OK;
+}
+
+// Band-only geometry (stencil scaled by a zero lambda) for A or A^T.
+LevelGeom blur_geom(const rls_problem* P, int transpose) {
+    LevelGeom g = P->lev[0].geom();
+    g.gv = (transpose ? P->atv : P->av).dev();
+    g.gh = (transpose ? P->ath : P->ah).dev();
+    return g;
+}
+
+rls_status upload_lam(rls_problem* P, const double* lam, int nlam,
+                      hipStream_t s) {
+    std::vector<double> l2(nlam);
+    for (int i = 0; i < nlam; ++i) {
+        if (!(lam[i] > 0.0) || !std::isfinite(lam[i]))
+            return fail(RLS_E_ARG, "lambda values must be finite and > 0");
+        l2[i] = lam[i] * lam[i];
+    }
+    RLS_HIP(hipMemcpyAsync(P->w.lam2.p, l2.data(), sizeof(double) * nlam,
+                           hipMemcpyHostToDevice, s));
+    return RLS_OK;
+}
+
+// Per-sweep, lambda-dependent preconditioner data: Gershgorin bounds and
+// Chebyshev coefficients per level, coarsest factorization per slot.
+rls_status prepare_sweep(rls_problem* P, int nslot, hipStream_t s) {
+    Work& w = P->w;
+    const int L = P->levels;
+    const int cs = 2 * P->nu;
+    for (int k = 0; k + 1 < L; ++k) {
+        double* rho = w.rho.as<double>() + (size_t)k * w.cap;
+        launch_gershgorin(P->lev[k].geom(), w.lam2.as<double>(), nslot, rho, s);
+        launch_cheb_coeffs(rho, nslot, P->ratio, P->nu,
+                           w.cheb.as<double>() + (size_t)k * w.cap * cs, s);
+    }
+    const Level& C = P->lev[L - 1];
+    const int nc = (int)C.n();
+    launch_coarse_assemble(C.geom(), w.lam2.as<double>(), nslot,
+                           w.kc.as<double>(), s);
+    launch_cholesky_inverse(w.kc.as<double>(), nc, nslot, w.winv.as<double>(),
+                            w.info.as<int>(), s);
+    RLS_TRY(check_launch("prepare_sweep"));
+    std::vector<int> info(nslot);
+    RLS_HIP(hipMemcpyAsync(info.data(), w.info.p, sizeof(int) * nslot,
+                           hipMemcpyDeviceToHost, s));
+    RLS_HIP(hipStreamSynchronize(s));
+    for (int i = 0; i < nslot; ++i)
+        if (info[i])
+            return fail(RLS_E_NOT_SPD,
+                        "coarsest matrix not positive definite (slot " +
+                            std::to_string(i) + ", pivot " +
+                            std::to_string(info[i]) + ")");
+    return RLS_OK;
+}
+
+// z = V-cycle(f) on level k (Algorithm 1, gamma = 1, V(nu, nu)).
+void vcycle(rls_problem* P, int k, int nslot, const int* active,
+            const double* f, double* z, hipStream_t s) {
+    Work& w = P->w;
+    const int L = P->levels;
+    if (k == L - 1) {
+        launch_coarse_solve(w.winv.as<double>(), (int)P->lev[k].n(), nslot,
+                            active, f, z, s);
+        return;
+    }
+    const Level& Lk = P->lev[k];
+    const LevelGeom g = Lk.geom();
+    const int cs = 2 * P->nu;
+    const double* cheb = w.cheb.as<double>() + (size_t)k * w.cap * cs;
+    double* xb = w.lxb[k].as<double>();
+    double* d = w.ld[k].as<double>();
+    double* t = w.lt[k].as<double>();
+    // 2 nu - 1 Chebyshev steps swap buffers; start in xb so that the
+    // result ends in z.
+    double* bufs[2] = {xb, z};
+    int cur = 0;
+    launch_jacobi_init(g, nslot, w.lam2.as<double>(), active, f, 0, cheb, cs,
+                       bufs[cur], d, s);
+    ApplyArgs a;
+    a.g = g;
+    a.nslot = nslot;
+    a.lam2 = w.lam2.as<double>();
+    a.active = active;
+    a.f = f;
+    a.d = d;
+    a.cheb_stride = cs;
+    for (int st = 1; st < P->nu; ++st) {
+        a.in = bufs[cur];
+        a.out = bufs[1 - cur];
+        a.cheb = cheb + 2 * st;
+        launch_apply(PRO_PLAIN, EPI_CHEB, a, s);
+        cur = 1 - cur;
+    }
+    // residual and restriction
+    a.in = bufs[cur];
+    a.out = t;
+    launch_apply(PRO_PLAIN, EPI_RESID, a, s);
+    const Level& Lc = P->lev[k + 1];
+    double* fc = w.lf[k + 1].as<double>();
+    double* zc = w.lx[k + 1].as<double>();
+    launch_restrict(g, Lc.geom(), nslot, active, t, fc, s);
+    vcycle(P, k + 1, nslot, active, fc, zc, s);
+    launch_prolong_add(g, Lc.geom(), nslot, active, zc, bufs[cur], s);
+    for (int st = 0; st < P->nu; ++st) {
+        a.in = bufs[cur];
+        a.out = bufs[1 - cur];
+        a.cheb = cheb + 2 * st;
+        launch_apply(PRO_PLAIN, EPI_CHEB, a, s);
+        cur = 1 - cur;
+    }
+}
+
+rls_status validate_grid(const rls_grid_desc* g) {
+    if (g->nv < 4 || g->nh < 4) return fail(RLS_E_ARG, "grid must be >= 4 x 4");
+    if (g->levels < 1 || g->levels > 16) return fail(RLS_E_ARG, "levels in 1..16");
+    if (g->nu < 1 || g->nu > 8) return fail(RLS_E_ARG, "nu in 1..8");
+    if (!(g->cheb_ratio > 1.0) || !std::isfinite(g->cheb_ratio))
+        return fail(RLS_E_ARG, "cheb_ratio must be > 1");
+    if (g->lbc != RLS_L_NEUMANN && g->lbc != RLS_L_PERIODIC)
+        return fail(RLS_E_ARG, "unknown gradient boundary");
+    for (int k = 0; k < g->levels; ++k) {
+        const int v = g->nv >> k, h = g->nh >> k;
+        if ((v << k) != g->nv || (h << k) != g->nh)
+            return fail(RLS_E_ARG, "grid not divisible by 2^(levels-1)");
+        if (v < 4 || h < 4)
+            return fail(RLS_E_ARG, "every level must be at least 4 x 4");
+    }
+    const int64_t nc = (int64_t)(g->nv >> (g->levels - 1)) * (g->nh >> (g->levels - 1));
+    if (nc > 1024)
+        return fail(RLS_E_ARG, "coarsest level exceeds 1024 unknowns; add levels");
+    if (g->precision != RLS_PREC_FP64)
+        return fail(RLS_E_UNSUPPORTED, "only RLS_PREC_FP64 is supported");
+    return RLS_OK;
+}
+
+}  // namespace
+
+// ====================================================================== ABI
+extern "C" {
+
+const char* rls_last_error(void) { return g_last_error.c_str(); }
+
+void rls_destroy(rls_problem* p) { delete p; }
+
+rls_status rls_setup(rls_problem** out, const rls_op_desc* A,
+                     const rls_grid_desc* g, const double* d, void* stream) {
+    g_last_error.clear();
+    if (!out || !A || !g) return fail(RLS_E_ARG, "null argument");
+    *out = nullptr;
+    RLS_TRY(validate_grid(g));
+    if (A->kind == RLS_OP_CSR)
+        return fail(RLS_E_UNSUPPORTED, "sparse operators are not supported yet");
+    if (A->kind != RLS_OP_BLUR_SEPARABLE) return fail(RLS_E_ARG, "unknown operator kind");
+    if (!A->taps_v || !A->taps_h) return fail(RLS_E_ARG, "null taps");
+    if (A->r_v < 0 || A->r_h < 0 || 2 * A->r_v + 1 > g->nv || 2 * A->r_h + 1 > g->nh)
+        return fail(RLS_E_ARG, "blur radius must satisfy 2r+1 <= n");
+    const int pair_ok = (A->bc == RLS_BC_PERIODIC && g->lbc == RLS_L_PERIODIC) ||
+                        (A->bc == RLS_BC_REFLECTIVE && g->lbc == RLS_L_NEUMANN) ||
+                        (A->bc == RLS_BC_ZERO && g->lbc == RLS_L_NEUMANN);
+    if (A->bc < 0 || A->bc > 2) return fail(RLS_E_ARG, "unknown blur boundary");
+    if (!pair_ok)
+        return fail(RLS_E_UNSUPPORTED,
+                    "supported (blur, gradient) boundary pairs: (periodic, "
+                    "periodic), (reflective, neumann), (zero, neumann)");
+    std::unique_ptr<rls_problem> P(new rls_problem());
+    RLS_HIP(hipGetDevice(&P->device));
+    P->nv = g->nv;
+    P->nh = g->nh;
+    P->levels = g->levels;
+    P->nu = g->nu;
+    P->ratio = g->cheb_ratio;
+    P->bc = A->bc;
+    P->lbc = g->lbc;
+    P->periodic = g->lbc == RLS_L_PERIODIC;
+    P->r_v = A->r_v;
+    P->r_h = A->r_h;
+    P->taps_v.assign(A->taps_v, A->taps_v + 2 * A->r_v + 1);
+    P->taps_h.assign(A->taps_h, A->taps_h + 2 * A->r_h + 1);
+    for (double t : P->taps_v)
+        if (!std::isfinite(t)) return fail(RLS_E_ARG, "non-finite tap");
+    for (double t : P->taps_h)
+        if (!std::isfinite(t)) return fail(RLS_E_ARG, "non-finite tap");
+    P->lev.resize(P->levels);
+    for (int k = 0; k < P->levels; ++k) {
+        P->lev[k].nv = P->nv >> k;
+        P->lev[k].nh = P->nh >> k;
+    }
+    hipStream_t s = (hipStream_t)stream;
+    RLS_TRY(build_direction(P.get(), P->taps_v, P->r_v, 0, s));
+    RLS_TRY(build_direction(P.get(), P->taps_h, P->r_h, 1, s));
+    RLS_TRY(install_weights(P.get(), d, s));
+    RLS_HIP(hipStreamSynchronize(s));
+    *out = P.release();
+    return RLS_OK;
+}
+
+rls_status rls_set_weights(rls_problem* p, const double* d, void* stream) {
+    g_last_error.clear();
+    if (!p) return fail(RLS_E_STATE, "null handle");
+    hipStream_t s = (hipStream_t)stream;
+    RLS_TRY(install_weights(p, d, s));
+    RLS_HIP(hipStreamSynchronize(s));
+    return RLS_OK;
+}
+
+rls_status rls_level_shape(const rls_problem* p, int level, int* nv, int* nh) {
+    if (!p) return fail(RLS_E_STATE, "null handle");
+    if (level < 0 || level >= p->levels) return fail(RLS_E_ARG, "level out of range");
+    if (nv) *nv = p->lev[level].nv;
+    if (nh) *nh = p->lev[level].nh;
+    return RLS_OK;
+}
+
+rls_status rls_get_stencil(const rls_problem* p, int level, double* out) {
+    if (!p) return fail(RLS_E_STATE, "null handle");
+    if (level < 0 || level >= p->levels || !out) return fail(RLS_E_ARG, "bad level/out");
+    const Level& L = p->lev[level];
+    RLS_HIP(hipMemcpy(out, L.planes.p, sizeof(double) * 5 * L.n(),
+                      hipMemcpyDeviceToHost));
+    return RLS_OK;
+}
+
+rls_status rls_get_gram_band(const rls_problem* p, int level, int dir, int* bw,
+                             double* out) {
+    if (!p) return fail(RLS_E_STATE, "null handle");
+    if (level < 0 || level >= p->levels || dir < 0 || dir > 1)
+        return fail(RLS_E_ARG, "bad level/direction");
+    const Band& B = dir == 0 ? p->lev[level].gv : p->lev[level].gh;
+    if (bw) *bw = B.bw;
+    if (out)
+        RLS_HIP(hipMemcpy(out, B.table.p, sizeof(double) * B.n * (2 * B.bw + 1),
+                          hipMemcpyDeviceToHost));
+    return RLS_OK;
+}
+
+rls_status rls_apply_normal(rls_problem* p, int level, const double* lam,
+                            int nlam, const double* v, double* out,
+                            void* stream) {
+    g_last_error.clear();
+    if (!p) return fail(RLS_E_STATE, "null handle");
+    if (level < 0 || level >= p->levels || nlam < 1 || !lam || !v || !out)
+        return fail(RLS_E_ARG, "bad arguments");
+    hipStream_t s = (hipStream_t)stream;
+    RLS_TRY(ensure_work(p, nlam));
+    RLS_TRY(upload_lam(p, lam, nlam, s));
+    ApplyArgs a;
+    a.g = p->lev[level].geom();
+    a.nslot = nlam;
+    a.lam2 = p->w.lam2.as<double>();
+    a.in = v;
+    a.out = out;
+    launch_apply(PRO_PLAIN, EPI_STORE, a, s);
+    RLS_TRY(check_launch("rls_apply_normal"));
+    RLS_HIP(hipStreamSynchronize(s));
+    return RLS_OK;
+}
+
+rls_status rls_gershgorin(rls_problem* p, int level, const double* lam,
+                          int nlam, double* rho, void* stream) {
+    g_last_error.clear();
+    if (!p) return fail(RLS_E_STATE, "null handle");
+    if (level < 0 || level >= p->levels || nlam < 1 || !lam || !rho)
+        return fail(RLS_E_ARG, "bad arguments");
+    hipStream_t s = (hipStream_t)stream;
+    RLS_TRY(ensure_work(p, nlam));
+    RLS_TRY(upload_lam(p, lam, nlam, s));
+    launch_gershgorin(p->lev[level].geom(), p->w.lam2.as<double>(), nlam,
+                      p->w.rho.as<double>(), s);
+    RLS_TRY(check_launch("rls_gershgorin"));
+    RLS_HIP(hipMemcpyAsync(rho, p->w.rho.p, sizeof(double) * nlam,
+                           hipMemcpyDeviceToHost, s));
+    RLS_HIP(hipStreamSynchronize(s));
+    return RLS_OK;
+}
+
+rls_status rls_vcycle(rls_problem* p, const double* lam, int nlam,
+                      const double* r, double* z, void* stream) {
+    g_last_error.clear();
+    if (!p) return fail(RLS_E_STATE, "null handle");
+    if (nlam < 1 || !lam || !r || !z) return fail(RLS_E_ARG, "bad arguments");
+    hipStream_t s = (hipStream_t)stream;
+    RLS_TRY(ensure_work(p, nlam));
+    RLS_TRY(upload_lam(p, lam, nlam, s));
+    RLS_TRY(prepare_sweep(p, nlam, s));
+    vcycle(p, 0, nlam, nullptr, r, z, s);
+    RLS_TRY(check_launch("rls_vcycle"));
+    RLS_HIP(hipStreamSynchronize(s));
+    return RLS_OK;
+}
+
+static rls_status apply_blur(rls_problem* p, int transpose, const double* x,
+                             double* y, int nvec, hipStream_t s) {
+    RLS_TRY(ensure_work(p, nvec));
+    ApplyArgs a;
+    a.g = blur_geom(p, transpose);
+    a.nslot = nvec;
+    a.lam2 = p->w.zero_lam2.as<double>();
+    a.in = x;
+    a.out = y;
+    launch_apply(PRO_PLAIN, EPI_STORE, a, s);
+    return check_launch("apply_blur");
+}
+
+rls_status rls_apply_forward(rls_problem* p, const double* x, double* y,
+                             int nvec, void* stream) {
+    g_last_error.clear();
+    if (!p) return fail(RLS_E_STATE, "null handle");
+    if (!x || !y || nvec < 1) return fail(RLS_E_ARG, "bad arguments");
+    hipStream_t s = (hipStream_t)stream;
+    RLS_TRY(apply_blur(p, 0, x, y, nvec, s));
+    RLS_HIP(hipStreamSynchronize(s));
+    return RLS_OK;
+}
+
+rls_status rls_apply_adjoint(rls_problem* p, const double* y, double* x,
+                             int nvec, void* stream) {
+    g_last_error.clear();
+    if (!p) return fail(RLS_E_STATE, "null handle");
+    if (!x || !y || nvec < 1) return fail(RLS_E_ARG, "bad arguments");
+    hipStream_t s = (hipStream_t)stream;
+    RLS_TRY(apply_blur(p, 1, y, x, nvec, s));
+    RLS_HIP(hipStreamSynchronize(s));
+    return RLS_OK;
+}
+
+rls_status rls_solve_sweep(rls_problem* p, const double* b, const double* lam,
+                           int nlam, double tol, const rls_sweep_opts* opts,
+                           const double* x0, double* x, double* resnorm,
+                           double* seminorm, rls_solve_info* info,
+                           void* stream) {
+    g_last_error.clear();
+    if (!p) return fail(RLS_E_STATE, "null handle");
+    if (!b || !x || !lam || nlam < 1) return fail(RLS_E_ARG, "bad arguments");
+    if (!(tol > 0.0) || !std::isfinite(tol)) return fail(RLS_E_ARG, "tol must be > 0");
+    rls_sweep_opts o{100000, RLS_TOL_RELATIVE, 20};
+    if (opts) o = *opts;
+    if (o.maxit < 1 || o.poll_every < 1 ||
+        (o.tol_mode != RLS_TOL_RELATIVE && o.tol_mode != RLS_TOL_ABSOLUTE))
+        return fail(RLS_E_ARG, "bad sweep options");
+    hipStream_t s = (hipStream_t)stream;
+    const int ns = nlam;
+    const int64_t n = p->n();
+    RLS_TRY(ensure_work(p, ns));
+    Work& w = p->w;
+    RLS_TRY(upload_lam(p, lam, nlam, s));
+    RLS_TRY(prepare_sweep(p, ns, s));
+    double* part = w.part.as<double>();
+    const int vb = vec_blocks(n);
+    const LevelGeom g0 = p->lev[0].geom();
+    const int tiles0 = apply_tiles(g0);
+    SlotState* st = w.st.as<SlotState>();
+    int* active = w.active.as<int>();
+    double* r = w.r.as<double>();
+    double* z = w.z.as<double>();
+    double* q = w.q.as<double>();
+    double* pb[2] = {w.p0.as<double>(), w.p1.as<double>()};
+    double* f = w.f.as<double>();
+    // f = A^T b and ||f||^2 (partials in the last slot row of `part`)
+    RLS_TRY(apply_blur(p, 1, b, f, 1, s));
+    DBuf fpbuf;
+    RLS_TRY(dalloc(fpbuf, sizeof(double) * vb));
+    double* fpart = fpbuf.as<double>();
+    launch_sumsq_slots(f, n, 1, fpart, s);
+    // x0 and the initial residual
+    ApplyArgs a;
+    a.g = g0;
+    a.nslot = ns;
+    a.lam2 = w.lam2.as<double>();
+    if (x0) {
+        if (x0 != x)
+            RLS_HIP(hipMemcpyAsync(x, x0, sizeof(double) * ns * n,
+                                   hipMemcpyDeviceToDevice, s));
+        a.in = x;
+        a.out = r;
+        a.f = f;
+        a.f_shared = 1;
+        launch_apply(PRO_PLAIN, EPI_RESID, a, s);
+    } else {
+        RLS_HIP(hipMemsetAsync(x, 0, sizeof(double) * ns * n, s));
+        launch_broadcast(f, n, ns, r, s);
+    }
+    // rr partials into q (scratch), rz partials into part
+    DBuf rrbuf;
+    RLS_TRY(dalloc(rrbuf, sizeof(double) * (size_t)ns * vb));
+    launch_sumsq_slots(r, n, ns, rrbuf.as<double>(), s);
+    vcycle(p, 0, ns, nullptr, r, z, s);
+    launch_dot(r, z, n, ns, nullptr, part, s);
+    launch_pcg_init(st, ns, fpart, vb, rrbuf.as<double>(), vb, part, vb, tol,
+                    o.tol_mode == RLS_TOL_ABSOLUTE, o.maxit, active, s);
+    RLS_HIP(hipMemsetAsync(pb[0], 0, sizeof(double) * ns * n, s));
+    RLS_HIP(hipMemsetAsync(w.beta.p, 0, sizeof(double) * ns, s));
+    RLS_TRY(check_launch("pcg init"));
+    int cur = 0;
+    std::vector<int> hact(ns);
+    for (int it = 0;; ++it) {
+        if (it % o.poll_every == 0) {
+            RLS_HIP(hipMemcpyAsync(hact.data(), active, sizeof(int) * ns,
+                                   hipMemcpyDeviceToHost, s));
+            RLS_HIP(hipStreamSynchronize(s));
+            bool any = false;
+            for (int v : hact) any |= v != 0;
+            if (!any) break;
+        }
+        // p = z + beta p ; q = K p ; partial p.q
+        a = ApplyArgs();
+        a.g = g0;
+        a.nslot = ns;
+        a.lam2 = w.lam2.as<double>();
+        a.active = active;
+        a.in = z;
+        a.pold = pb[cur];
+        a.pnew = pb[1 - cur];
+        a.beta = w.beta.as<double>();
+        a.out = q;
+        a.part = part;
+        launch_apply(PRO_PUPDATE, EPI_DOT, a, s);
+        launch_finalize_alpha(st, ns, part, tiles0, active, s);
+        launch_update_xr(st, n, ns, x, r, pb[1 - cur], q, part, s);
+        launch_finalize_rr(st, ns, part, vb, active, s);
+        vcycle(p, 0, ns, active, r, z, s);
+        launch_dot(r, z, n, ns, active, part, s);
+        launch_finalize_beta(st, ns, part, vb, w.beta.as<double>(), active, s);
+        cur = 1 - cur;
+        RLS_TRY(check_launch("pcg iteration"));
+    }
+    // true residual, L-curve pair
+    a = ApplyArgs();
+    a.g = g0;
+    a.nslot = ns;
+    a.lam2 = w.lam2.as<double>();
+    a.in = x;
+    a.out = q;
+    a.f = f;
+    a.f_shared = 1;
+    launch_apply(PRO_PLAIN, EPI_RESID, a, s);
+    std::vector<double> hv(ns);
+    DBuf outv;
+    RLS_TRY(dalloc(outv, sizeof(double) * 3 * ns));
+    double* o_true = outv.as<double>();
+    double* o_res = o_true + ns;
+    double* o_sem = o_true + 2 * ns;
+    launch_sumsq_slots(q, n, ns, part, s);
+    launch_reduce_slots(part, vb, ns, o_true, s);
+    RLS_TRY(apply_blur(p, 0, x, w.y.as<double>(), ns, s));
+    launch_sub_sumsq(w.y.as<double>(), b, n, ns, part, s);
+    launch_reduce_slots(part, vb, ns, o_res, s);
+    launch_weighted_grad_sq(x, p->unit_weights ? nullptr : p->weights.as<double>(),
+                            p->nv, p->nh, p->periodic, ns, part, s);
+    launch_reduce_slots(part, vb, ns, o_sem, s);
+    RLS_TRY(check_launch("sweep outputs"));
+    std::vector<double> h3(3 * ns);
+    std::vector<SlotState> hst(ns);
+    RLS_HIP(hipMemcpyAsync(h3.data(), o_true, sizeof(double) * 3 * ns,
+                           hipMemcpyDeviceToHost, s));
+    RLS_HIP(hipMemcpyAsync(hst.data(), st, sizeof(SlotState) * ns,
+                           hipMemcpyDeviceToHost, s));
+    RLS_HIP(hipStreamSynchronize(s));
+    for (int i = 0; i < ns; ++i) {
+        if (resnorm) resnorm[i] = std::sqrt(h3[ns + i]);
+        if (seminorm) seminorm[i] = std::sqrt(h3[2 * ns + i]);
+        if (info) {
+            const double fn = hst[i].fnorm > 0 ? hst[i].fnorm : 1.0;
+            info[i].iters = hst[i].it;
+            info[i].flags = hst[i].flags;
+            info[i].relres = std::sqrt(hst[i].rr) / fn;
+            info[i].relres_true = std::sqrt(h3[i]) / fn;
+        }
+    }
+    return RLS_OK;
+}
+
+}  // extern "C"

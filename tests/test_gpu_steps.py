@@ -1,0 +1,137 @@
+"""Step-level parity of the HIP path against the CPU oracle.
+
+Each test runs one step of the solver through the C-ABI (librls.so) and
+compares it element by element with the oracle on the same seeded inputs:
+the lambda-free hierarchy (Gram bands, Galerkin stencils), the level
+operator K_k(lambda), the Gershgorin bounds, the V-cycle and the forward
+operator.  Floating-point bar: relative 1e-12 for single products, 1e-10
+for the V-cycle (a composition of ~30 products and a Cholesky solve), all in
+FP64 on both sides.
+"""
+import numpy as np
+import pytest
+import scipy.sparse as sp
+
+import workloads as W
+from oracle.pcg import DeblurOracle
+from tests.gpu_util import band_from_dense, dev, host, planes_from_sparse
+
+pytestmark = pytest.mark.gpu
+
+CASES = {
+    # name: (nv, nh, r, sigma, bc, lbc, levels)
+    "periodic64": (64, 64, 4, 2.0, "periodic", "periodic", 3),
+    "reflective96x72": (96, 72, 3, 1.5, "reflective", "neumann", 3),
+    "zero64x48": (64, 48, 2, 1.0, "zero", "neumann", 3),
+    "reflective32_one_level": (32, 32, 2, 1.0, "reflective", "neumann", 1),
+}
+
+
+def _build(name, seed=0):
+    from paper_2306_11067_amd import Problem
+    nv, nh, r, sg, bc, lbc, levels = CASES[name]
+    rng = np.random.default_rng(100 + seed)
+    tv = W.gaussian_taps(r, sg)
+    th = W.gaussian_taps(max(1, r - 1), sg * 0.8)
+    d = rng.uniform(0.01, 1.0, 2 * nv * nh)
+    O = DeblurOracle(nv, nh, tv, th, bc, lbc, d, levels)
+    P = Problem(nv, nh, tv, th, bc, lbc, levels, nu=2, cheb_ratio=4.0,
+                weights=dev(d))
+    return O, P, rng
+
+
+@pytest.mark.parametrize("name", list(CASES))
+def test_gram_bands_match_one_sided_hierarchy(name):
+    O, P, _ = _build(name)
+    H = O.H
+    for k in range(H.levels):
+        for direction, A1 in ((0, H.A[k].Av), (1, H.A[k].Ah)):
+            G = (A1.T @ A1).toarray()
+            want, _ = band_from_dense(G, O.lbc == "periodic")
+            got = P.gram_band(k, direction)
+            bw_w = (want.shape[1] - 1) // 2
+            bw_g = (got.shape[1] - 1) // 2
+            assert bw_g >= bw_w
+            if bw_g > bw_w:   # extra diagonals of the GPU band must be zero
+                assert np.abs(got[:, :bw_g - bw_w]).max() < 1e-15
+                assert np.abs(got[:, bw_g + bw_w + 1:]).max() < 1e-15
+                got = got[:, bw_g - bw_w:bw_g + bw_w + 1]
+            np.testing.assert_allclose(got, want, rtol=0,
+                                       atol=1e-14 * np.abs(want).max())
+
+
+@pytest.mark.parametrize("name", list(CASES))
+def test_galerkin_stencils_match_oracle(name):
+    O, P, _ = _build(name)
+    H = O.H
+    for k in range(H.levels):
+        S = (H.M[k].T @ H.M[k]).tocsr()
+        want = planes_from_sparse(S, H.nv[k], H.nh[k], O.lbc == "periodic")
+        got = P.stencil(k)
+        np.testing.assert_allclose(got, want, rtol=0,
+                                   atol=1e-13 * np.abs(want).max())
+
+
+@pytest.mark.parametrize("name", list(CASES))
+def test_level_operator_matches_oracle(name):
+    O, P, rng = _build(name)
+    H = O.H
+    lams = np.array([1e-4, 3e-2, 1.0, 7.0])
+    for k in range(H.levels):
+        nk = H.nv[k] * H.nh[k]
+        v = rng.standard_normal(len(lams) * nk)
+        got = host(P.apply_normal(k, lams, dev(v))).reshape(len(lams), nk)
+        for s, lam in enumerate(lams):
+            want = H.K(k, lam, v[s * nk:(s + 1) * nk])
+            err = np.abs(got[s] - want).max() / np.abs(want).max()
+            assert err < 1e-12, (k, lam, err)
+
+
+@pytest.mark.parametrize("name", list(CASES))
+def test_gershgorin_bounds_match_oracle(name):
+    O, P, _ = _build(name)
+    H = O.H
+    lams = np.array([1e-5, 1e-2, 0.5, 20.0])
+    for k in range(H.levels):
+        got = P.gershgorin(k, lams)
+        want = np.array([H.gershgorin(k, lam) for lam in lams])
+        np.testing.assert_allclose(got, want, rtol=1e-12)
+
+
+@pytest.mark.parametrize("name", list(CASES))
+def test_vcycle_matches_oracle(name):
+    O, P, rng = _build(name)
+    n = O.nv * O.nh
+    lams = np.array([1e-4, 1e-2, 1.0])
+    r = rng.standard_normal(len(lams) * n)
+    got = host(P.vcycle(lams, dev(r))).reshape(len(lams), n)
+    for s, lam in enumerate(lams):
+        want = O.vcycle(lam, nu=2, ratio=4.0)(r[s * n:(s + 1) * n])
+        err = np.abs(got[s] - want).max() / np.abs(want).max()
+        assert err < 1e-10, (lam, err)
+
+
+@pytest.mark.parametrize("name", list(CASES))
+def test_forward_and_adjoint_match_oracle(name):
+    O, P, rng = _build(name)
+    n = O.nv * O.nh
+    x = rng.standard_normal(2 * n)
+    y = host(P.forward(dev(x), nvec=2))
+    z = host(P.adjoint(dev(x), nvec=2))
+    for s in range(2):
+        xs = x[s * n:(s + 1) * n]
+        np.testing.assert_allclose(y[s * n:(s + 1) * n], O.A.matvec(xs),
+                                   rtol=0, atol=1e-14 * np.abs(xs).max())
+        np.testing.assert_allclose(z[s * n:(s + 1) * n], O.A.rmatvec(xs),
+                                   rtol=0, atol=1e-14 * np.abs(xs).max())
+
+
+def test_unit_weights_stencil_is_laplacian():
+    from paper_2306_11067_amd import Problem
+    nv = nh = 32
+    t = W.gaussian_taps(2, 1.0)
+    P = Problem(nv, nh, t, t, "reflective", "neumann", 3)
+    from oracle import operators as ops
+    L = ops.gradient(nv, nh, "neumann")
+    want = planes_from_sparse((L.T @ L).tocsr(), nv, nh, False)
+    np.testing.assert_allclose(P.stencil(0), want, atol=0)
