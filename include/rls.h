@@ -117,6 +117,8 @@ typedef struct {
     int maxit;              /* PCG iteration cap per lambda (>= 1)           */
     int tol_mode;           /* RLS_TOL_RELATIVE / RLS_TOL_ABSOLUTE           */
     int poll_every;         /* host convergence check period, iterations     */
+    int graph;              /* 1: replay iteration chunks as HIP graphs;
+                               0: launch kernels one by one (same results)   */
 } rls_sweep_opts;
 
 typedef struct {
@@ -150,7 +152,7 @@ rls_status rls_set_weights(rls_problem* p, const double* d, void* stream);
  * b:        device, n values (the data; A is square for the blur).
  * lam:      host, nlam values > 0.
  * tol:      > 0, see opts->tol_mode (NULL opts: relative, maxit 100000,
- *           poll every 20 iterations).
+ *           poll every 32 iterations, graphs on).
  * x0:       device, nlam*n initial guesses, or NULL for zero.
  * x:        device, nlam*n solutions (may alias x0).
  * resnorm:  host, nlam values ||A x_i - b||_2 (may be NULL).

@@ -94,14 +94,15 @@ class Problem:
         _check(self._lib.rls_set_weights(self._h, d, _stream()))
 
     def solve_sweep(self, b, lams, tol, x0=None, x=None, maxit=100000,
-                    tol_mode="relative", poll_every=20):
+                    tol_mode="relative", poll_every=32, graph=True):
         import torch
         lam, plam = _dbl(lams)
         nl = len(lam)
         if x is None:
             x = torch.empty(nl * self.n, dtype=torch.float64, device=b.device)
         opts = L.SweepOpts(int(maxit), L.RLS_TOL_ABSOLUTE if tol_mode ==
-                           "absolute" else L.RLS_TOL_RELATIVE, int(poll_every))
+                           "absolute" else L.RLS_TOL_RELATIVE, int(poll_every),
+                           1 if graph else 0)
         res = np.zeros(nl)
         sem = np.zeros(nl)
         info = (L.SolveInfo * nl)()

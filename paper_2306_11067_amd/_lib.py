@@ -53,7 +53,7 @@ class GridDesc(C.Structure):
 
 class SweepOpts(C.Structure):
     _fields_ = [("maxit", C.c_int), ("tol_mode", C.c_int),
-                ("poll_every", C.c_int)]
+                ("poll_every", C.c_int), ("graph", C.c_int)]
 
 
 class SolveInfo(C.Structure):

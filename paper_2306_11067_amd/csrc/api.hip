@@ -121,6 +121,14 @@ struct Work {
     int cap = 0;                 // slots allocated
     DBuf lam2, zero_lam2, st, active, beta, part, rho, cheb, kc, winv, info;
     DBuf f;                      // A^T b (n)
+    DBuf fpart, rrpart, outv, slots;
+    DBuf part_pq, part_rr, part_rz;    // PCG partial sums per slot
+    int* h_active = nullptr;     // pinned host mirrors
+    int* h_slots = nullptr;
+    ~Work() {
+        if (h_active) hipHostFree(h_active);
+        if (h_slots) hipHostFree(h_slots);
+    }
     DBuf r, z, p0, p1, q, y;     // fine vectors (cap * n)
     std::vector<DBuf> lx, lxb, ld, lt, lf;   // per level (cap * n_k)
 };
@@ -139,7 +147,12 @@ struct rls_problem {
     DBuf weights;                // 2n, or empty for D = I
     int unit_weights = 1;
     Work w;
+    hipStream_t cstream = nullptr;   // capture stream for iteration graphs
+    int kt = 0;                      // first level handled by the tail kernel
     int64_t n() const { return (int64_t)nv * nh; }
+    ~rls_problem() {
+        if (cstream) hipStreamDestroy(cstream);
+    }
 };
 
 namespace {
@@ -177,6 +190,21 @@ rls_status ensure_work(rls_problem* P, int nslot) {
     RLS_TRY(dalloc(w.winv, sizeof(double) * (size_t)cap * 2 * nc * nc));
     RLS_TRY(dalloc(w.info, sizeof(int) * cap));
     RLS_TRY(dalloc(w.f, sizeof(double) * n));
+    RLS_TRY(dalloc(w.fpart, sizeof(double) * vec_blocks(n)));
+    RLS_TRY(dalloc(w.rrpart, sizeof(double) * (size_t)cap * vec_blocks(n)));
+    RLS_TRY(dalloc(w.outv, sizeof(double) * 3 * cap));
+    RLS_TRY(dalloc(w.slots, sizeof(int) * cap));
+    {
+        const int t0 = apply_tiles(P->lev[0].geom());
+        RLS_TRY(dalloc(w.part_pq, sizeof(double) * (size_t)cap * t0));
+        RLS_TRY(dalloc(w.part_rz, sizeof(double) * (size_t)cap * t0));
+        RLS_TRY(dalloc(w.part_rr, sizeof(double) * (size_t)cap * vec_blocks(n)));
+    }
+    if (w.h_active) hipHostFree(w.h_active);
+    if (w.h_slots) hipHostFree(w.h_slots);
+    w.h_active = w.h_slots = nullptr;
+    RLS_HIP(hipHostMalloc((void**)&w.h_active, sizeof(int) * cap, hipHostMallocDefault));
+    RLS_HIP(hipHostMalloc((void**)&w.h_slots, sizeof(int) * cap, hipHostMallocDefault));
     for (DBuf* b : {&w.r, &w.z, &w.p0, &w.p1, &w.q, &w.y})
         RLS_TRY(dalloc(*b, sizeof(double) * (size_t)cap * n));
     w.lx.resize(L);
@@ -374,59 +402,148 @@ rls_status prepare_sweep(rls_problem* P, int nslot, hipStream_t s) {
     return RLS_OK;
 }
 
-// z = V-cycle(f) on level k (Algorithm 1, gamma = 1, V(nu, nu)).
-void vcycle(rls_problem* P, int k, int nslot, const int* active,
-            const double* f, double* z, hipStream_t s) {
+// PCG control folded into the level-0 kernels of a V-cycle: a convergence
+// test in the first kernel, partial sums of r . z in the last.
+struct CycleCtl {
+    int gate = 0;
+    SlotState* st = nullptr;
+    int* active_w = nullptr;
+    const double* part_rr = nullptr;
+    int nrr = 0;
+    double* dot_part = nullptr;
+    int dot_stride = 0;
+};
+
+// z = V-cycle(f) on level k (Algorithm 1, gamma = 1, V(nu, nu)), for the
+// nslot slots listed in `slots` (null: slots 0..nslot-1).
+void vcycle(rls_problem* P, int k, int nslot, const int* slots,
+            const int* active, const double* f, double* z, const CycleCtl& ctl,
+            hipStream_t s) {
     Work& w = P->w;
     const int L = P->levels;
-    if (k == L - 1) {
-        launch_coarse_solve(w.winv.as<double>(), (int)P->lev[k].n(), nslot,
-                            active, f, z, s);
+    const int cs = 2 * P->nu;
+    const int nu = P->nu;
+    const bool top = k == 0;
+    if (k >= P->kt) {
+        TailArgs t;
+        t.nlev = L - k;
+        for (int i = 0; i < t.nlev; ++i) {
+            const LevelGeom g = P->lev[k + i].geom();
+            t.lev[i].nv = g.nv;
+            t.lev[i].nh = g.nh;
+            t.lev[i].gv = g.gv;
+            t.lev[i].gh = g.gh;
+            t.lev[i].S = g.S;
+            t.lev[i].cheb = w.cheb.as<double>() + (size_t)(k + i) * w.cap * cs;
+        }
+        t.nu = nu;
+        t.cheb_stride = cs;
+        t.periodic = P->periodic;
+        t.lam2 = w.lam2.as<double>();
+        t.slots = slots;
+        t.active = active;
+        t.f = f;
+        t.z = z;
+        t.W = w.winv.as<double>();
+        if (top) {
+            t.gate = ctl.gate;
+            t.st = ctl.st;
+            t.active_w = ctl.active_w;
+            t.part_rr = ctl.part_rr;
+            t.nrr = ctl.nrr;
+            t.dot = ctl.dot_part != nullptr;
+            t.part = ctl.dot_part;
+            t.part_stride = ctl.dot_stride;
+        }
+        launch_tail(t, nslot, s);
         return;
     }
-    const Level& Lk = P->lev[k];
-    const LevelGeom g = Lk.geom();
-    const int cs = 2 * P->nu;
+    const LevelGeom g = P->lev[k].geom();
     const double* cheb = w.cheb.as<double>() + (size_t)k * w.cap * cs;
-    double* xb = w.lxb[k].as<double>();
     double* d = w.ld[k].as<double>();
-    double* t = w.lt[k].as<double>();
-    // 2 nu - 1 Chebyshev steps swap buffers; start in xb so that the
-    // result ends in z.
-    double* bufs[2] = {xb, z};
-    int cur = 0;
-    launch_jacobi_init(g, nslot, w.lam2.as<double>(), active, f, 0, cheb, cs,
-                       bufs[cur], d, s);
     ApplyArgs a;
     a.g = g;
     a.nslot = nslot;
+    a.slots = slots;
     a.lam2 = w.lam2.as<double>();
     a.active = active;
     a.f = f;
     a.d = d;
     a.cheb_stride = cs;
-    for (int st = 1; st < P->nu; ++st) {
-        a.in = bufs[cur];
-        a.out = bufs[1 - cur];
-        a.cheb = cheb + 2 * st;
-        launch_apply(PRO_PLAIN, EPI_CHEB, a, s);
-        cur = 1 - cur;
-    }
-    // residual and restriction
-    a.in = bufs[cur];
-    a.out = t;
-    launch_apply(PRO_PLAIN, EPI_RESID, a, s);
-    const Level& Lc = P->lev[k + 1];
+    a.cheb_first = cheb;
+    auto gate_first = [&](ApplyArgs& aa) {
+        if (top && ctl.gate) {
+            aa.gate = 1;
+            aa.st = ctl.st;
+            aa.active_w = ctl.active_w;
+            aa.part_rr = ctl.part_rr;
+            aa.nrr = ctl.nrr;
+        }
+    };
     double* fc = w.lf[k + 1].as<double>();
     double* zc = w.lx[k + 1].as<double>();
-    launch_restrict(g, Lc.geom(), nslot, active, t, fc, s);
-    vcycle(P, k + 1, nslot, active, fc, zc, s);
-    launch_prolong_add(g, Lc.geom(), nslot, active, zc, bufs[cur], s);
-    for (int st = 0; st < P->nu; ++st) {
-        a.in = bufs[cur];
-        a.out = bufs[1 - cur];
-        a.cheb = cheb + 2 * st;
-        launch_apply(PRO_PLAIN, EPI_CHEB, a, s);
+    if (nu == 1) {
+        // x1 = c f / diag never leaves the tiles: the restriction kernel
+        // forms it on the fly, the correction kernel forms it again.
+        ApplyArgs r = a;
+        gate_first(r);
+        r.fc = fc;
+        launch_apply(PRO_JACOBI, EPI_RESTRICT, r, s);
+        vcycle(P, k + 1, nslot, slots, active, fc, zc, CycleCtl(), s);
+        ApplyArgs c = a;
+        c.ec = zc;
+        c.out = z;
+        c.cheb = cheb;
+        if (top && ctl.dot_part) {
+            c.dot = 1;
+            c.part = ctl.dot_part;
+            c.part_stride = ctl.dot_stride;
+        }
+        launch_apply(PRO_PROLONG_JAC, EPI_CHEB, c, s);
+        return;
+    }
+    // nu >= 2.  Buffer writes: the first pre-smoothing step writes buffer 0,
+    // nu - 2 more pre steps and nu post steps each swap; choose buffer 0 so
+    // that the result lands in z.
+    const int swaps = (nu - 2) + nu;
+    double* bufs[2];
+    bufs[swaps % 2 == 0 ? 0 : 1] = z;
+    bufs[swaps % 2 == 0 ? 1 : 0] = w.lxb[k].as<double>();
+    int cur = 0;
+    {
+        ApplyArgs j = a;
+        gate_first(j);
+        j.out = bufs[cur];
+        j.cheb = cheb + 2;
+        launch_apply(PRO_JACOBI, EPI_CHEB, j, s);   // x1 = c f / diag, step 2
+    }
+    for (int st = 2; st < nu; ++st) {
+        ApplyArgs c = a;
+        c.in = bufs[cur];
+        c.out = bufs[1 - cur];
+        c.cheb = cheb + 2 * st;
+        launch_apply(PRO_PLAIN, EPI_CHEB, c, s);
+        cur = 1 - cur;
+    }
+    {
+        ApplyArgs r = a;                            // residual + restriction
+        r.in = bufs[cur];
+        r.fc = fc;
+        launch_apply(PRO_PLAIN, EPI_RESTRICT, r, s);
+    }
+    vcycle(P, k + 1, nslot, slots, active, fc, zc, CycleCtl(), s);
+    for (int st = 0; st < nu; ++st) {              // correction + smoothing
+        ApplyArgs c = a;
+        c.in = bufs[cur];
+        c.out = bufs[1 - cur];
+        c.cheb = cheb + 2 * st;
+        c.ec = st == 0 ? zc : nullptr;
+        if (top && ctl.dot_part && st == nu - 1) {
+            c.dot = 1;
+            c.part = ctl.dot_part;
+            c.part_stride = ctl.dot_stride;
+        }
+        launch_apply(st == 0 ? PRO_PROLONG : PRO_PLAIN, EPI_CHEB, c, s);
         cur = 1 - cur;
     }
 }
@@ -485,6 +602,8 @@ rls_status rls_setup(rls_problem** out, const rls_op_desc* A,
                     "periodic), (reflective, neumann), (zero, neumann)");
     std::unique_ptr<rls_problem> P(new rls_problem());
     RLS_HIP(hipGetDevice(&P->device));
+    RLS_HIP(hipStreamCreateWithFlags(&P->cstream, hipStreamNonBlocking));
+    configure_apply_kernels();
     P->nv = g->nv;
     P->nh = g->nh;
     P->levels = g->levels;
@@ -506,6 +625,10 @@ rls_status rls_setup(rls_problem** out, const rls_op_desc* A,
         P->lev[k].nv = P->nv >> k;
         P->lev[k].nh = P->nh >> k;
     }
+    P->kt = P->levels - 1;
+    while (P->kt > 0 && P->lev[P->kt - 1].n() <= TAIL_MAX_POINTS &&
+           P->levels - (P->kt - 1) <= TAIL_MAX_LEVELS)
+        --P->kt;
     hipStream_t s = (hipStream_t)stream;
     RLS_TRY(build_direction(P.get(), P->taps_v, P->r_v, 0, s));
     RLS_TRY(build_direction(P.get(), P->taps_h, P->r_h, 1, s));
@@ -603,7 +726,7 @@ rls_status rls_vcycle(rls_problem* p, const double* lam, int nlam,
     RLS_TRY(ensure_work(p, nlam));
     RLS_TRY(upload_lam(p, lam, nlam, s));
     RLS_TRY(prepare_sweep(p, nlam, s));
-    vcycle(p, 0, nlam, nullptr, r, z, s);
+    vcycle(p, 0, nlam, nullptr, nullptr, r, z, CycleCtl(), s);
     RLS_TRY(check_launch("rls_vcycle"));
     RLS_HIP(hipStreamSynchronize(s));
     return RLS_OK;
@@ -653,7 +776,7 @@ rls_status rls_solve_sweep(rls_problem* p, const double* b, const double* lam,
     if (!p) return fail(RLS_E_STATE, "null handle");
     if (!b || !x || !lam || nlam < 1) return fail(RLS_E_ARG, "bad arguments");
     if (!(tol > 0.0) || !std::isfinite(tol)) return fail(RLS_E_ARG, "tol must be > 0");
-    rls_sweep_opts o{100000, RLS_TOL_RELATIVE, 20};
+    rls_sweep_opts o{100000, RLS_TOL_RELATIVE, 32, 1};
     if (opts) o = *opts;
     if (o.maxit < 1 || o.poll_every < 1 ||
         (o.tol_mode != RLS_TOL_RELATIVE && o.tol_mode != RLS_TOL_ABSOLUTE))
@@ -676,13 +799,12 @@ rls_status rls_solve_sweep(rls_problem* p, const double* b, const double* lam,
     double* q = w.q.as<double>();
     double* pb[2] = {w.p0.as<double>(), w.p1.as<double>()};
     double* f = w.f.as<double>();
-    // f = A^T b and ||f||^2 (partials in the last slot row of `part`)
+    double* fpart = w.fpart.as<double>();
+    double* rrpart = w.rrpart.as<double>();
+    // f = A^T b and partial sums of ||f||^2
     RLS_TRY(apply_blur(p, 1, b, f, 1, s));
-    DBuf fpbuf;
-    RLS_TRY(dalloc(fpbuf, sizeof(double) * vb));
-    double* fpart = fpbuf.as<double>();
     launch_sumsq_slots(f, n, 1, fpart, s);
-    // x0 and the initial residual
+    // x0 and the initial residual r0 = f - K x0
     ApplyArgs a;
     a.g = g0;
     a.nslot = ns;
@@ -700,51 +822,114 @@ rls_status rls_solve_sweep(rls_problem* p, const double* b, const double* lam,
         RLS_HIP(hipMemsetAsync(x, 0, sizeof(double) * ns * n, s));
         launch_broadcast(f, n, ns, r, s);
     }
-    // rr partials into q (scratch), rz partials into part
-    DBuf rrbuf;
-    RLS_TRY(dalloc(rrbuf, sizeof(double) * (size_t)ns * vb));
-    launch_sumsq_slots(r, n, ns, rrbuf.as<double>(), s);
-    vcycle(p, 0, ns, nullptr, r, z, s);
-    launch_dot(r, z, n, ns, nullptr, part, s);
-    launch_pcg_init(st, ns, fpart, vb, rrbuf.as<double>(), vb, part, vb, tol,
+    launch_sumsq_slots(r, n, ns, rrpart, s);
+    // z0 = M r0 with partial sums of r0 . z0 (consumed by the first
+    // iteration, where beta = 0 makes p0 = z0)
+    {
+        CycleCtl c0;
+        c0.dot_part = w.part_rz.as<double>();
+        c0.dot_stride = tiles0;
+        vcycle(p, 0, ns, nullptr, nullptr, r, z, c0, s);
+    }
+    launch_pcg_init(st, ns, fpart, vb, rrpart, vb, tol,
                     o.tol_mode == RLS_TOL_ABSOLUTE, o.maxit, active, s);
     RLS_HIP(hipMemsetAsync(pb[0], 0, sizeof(double) * ns * n, s));
-    RLS_HIP(hipMemsetAsync(w.beta.p, 0, sizeof(double) * ns, s));
     RLS_TRY(check_launch("pcg init"));
-    int cur = 0;
-    std::vector<int> hact(ns);
-    for (int it = 0;; ++it) {
-        if (it % o.poll_every == 0) {
-            RLS_HIP(hipMemcpyAsync(hact.data(), active, sizeof(int) * ns,
-                                   hipMemcpyDeviceToHost, s));
-            RLS_HIP(hipStreamSynchronize(s));
-            bool any = false;
-            for (int v : hact) any |= v != 0;
-            if (!any) break;
+
+    // One PCG iteration (parity `cur`) for the `nact` slots in w.slots:
+    //   p = z + beta p, q = K p, partials of p . q      (beta folded in)
+    //   x += alpha p, r -= alpha q, partials of ||r||^2 (alpha folded in)
+    //   z = M r with the convergence test first and partials of r . z last
+    auto iteration = [&](int nact, int cur, hipStream_t ss) {
+        const int* sl = w.slots.as<int>();
+        ApplyArgs ak;
+        ak.g = g0;
+        ak.nslot = nact;
+        ak.slots = sl;
+        ak.lam2 = w.lam2.as<double>();
+        ak.active = active;
+        ak.in = z;
+        ak.pold = pb[cur];
+        ak.pnew = pb[1 - cur];
+        ak.out = q;
+        ak.part = w.part_pq.as<double>();
+        ak.part_stride = tiles0;
+        ak.st = st;
+        ak.active_w = active;
+        ak.part_rz = w.part_rz.as<double>();
+        ak.nrz = tiles0;
+        ak.parity = cur;
+        launch_apply(PRO_PUPDATE, EPI_DOT, ak, ss);
+        launch_update_xr(st, active, sl, n, nact, x, r, pb[1 - cur], q,
+                         w.part_pq.as<double>(), tiles0, cur,
+                         w.part_rr.as<double>(), ss);
+        CycleCtl c;
+        c.gate = 1;
+        c.st = st;
+        c.active_w = active;
+        c.part_rr = w.part_rr.as<double>();
+        c.nrr = vb;
+        c.dot_part = w.part_rz.as<double>();
+        c.dot_stride = tiles0;
+        vcycle(p, 0, nact, sl, active, r, z, c, ss);
+    };
+
+    // Iterate in chunks of `chunk` iterations (even, so that the p buffers
+    // return to the same roles), polling the active flags between chunks.
+    // With graphs, a chunk is captured once per active-slot count and
+    // replayed.
+    const int chunk = o.poll_every + (o.poll_every & 1);
+    int* hact = w.h_active;
+    int* hsl = w.h_slots;
+    hipGraphExec_t exec = nullptr;
+    int exec_nact = -1;
+    rls_status status = RLS_OK;
+    for (;;) {
+        RLS_HIP(hipMemcpyAsync(hact, active, sizeof(int) * ns,
+                               hipMemcpyDeviceToHost, s));
+        RLS_HIP(hipStreamSynchronize(s));
+        int nact = 0;
+        for (int i = 0; i < ns; ++i)
+            if (hact[i]) hsl[nact++] = i;
+        if (nact == 0) break;
+        RLS_HIP(hipMemcpyAsync(w.slots.p, hsl, sizeof(int) * nact,
+                               hipMemcpyHostToDevice, s));
+        if (!o.graph) {
+            for (int k = 0; k < chunk; ++k) iteration(nact, k & 1, s);
+            status = check_launch("pcg iteration");
+            if (status != RLS_OK) break;
+            continue;
         }
-        // p = z + beta p ; q = K p ; partial p.q
-        a = ApplyArgs();
-        a.g = g0;
-        a.nslot = ns;
-        a.lam2 = w.lam2.as<double>();
-        a.active = active;
-        a.in = z;
-        a.pold = pb[cur];
-        a.pnew = pb[1 - cur];
-        a.beta = w.beta.as<double>();
-        a.out = q;
-        a.part = part;
-        launch_apply(PRO_PUPDATE, EPI_DOT, a, s);
-        launch_finalize_alpha(st, ns, part, tiles0, active, s);
-        launch_update_xr(st, n, ns, x, r, pb[1 - cur], q, part, s);
-        launch_finalize_rr(st, ns, part, vb, active, s);
-        vcycle(p, 0, ns, active, r, z, s);
-        launch_dot(r, z, n, ns, active, part, s);
-        launch_finalize_beta(st, ns, part, vb, w.beta.as<double>(), active, s);
-        cur = 1 - cur;
-        RLS_TRY(check_launch("pcg iteration"));
+        if (nact != exec_nact) {
+            if (exec) hipGraphExecDestroy(exec);
+            exec = nullptr;
+            hipGraph_t graph = nullptr;
+            hipError_t e = hipStreamBeginCapture(p->cstream,
+                                                 hipStreamCaptureModeRelaxed);
+            if (e == hipSuccess) {
+                for (int k = 0; k < chunk; ++k) iteration(nact, k & 1, p->cstream);
+                e = hipStreamEndCapture(p->cstream, &graph);
+            }
+            if (e == hipSuccess) e = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
+            if (graph) hipGraphDestroy(graph);
+            if (e != hipSuccess) {
+                status = fail(RLS_E_HIP, std::string("graph capture: ") +
+                                             hipGetErrorString(e));
+                break;
+            }
+            exec_nact = nact;
+        }
+        hipError_t e = hipGraphLaunch(exec, s);
+        if (e != hipSuccess) {
+            status = fail(RLS_E_HIP, std::string("hipGraphLaunch: ") +
+                                         hipGetErrorString(e));
+            break;
+        }
     }
-    // true residual, L-curve pair
+    if (exec) hipGraphExecDestroy(exec);
+    if (status != RLS_OK) return status;
+
+    // true residual ||f - K x||, L-curve pair (||A x - b||, ||D L x||)
     a = ApplyArgs();
     a.g = g0;
     a.nslot = ns;
@@ -754,10 +939,7 @@ rls_status rls_solve_sweep(rls_problem* p, const double* b, const double* lam,
     a.f = f;
     a.f_shared = 1;
     launch_apply(PRO_PLAIN, EPI_RESID, a, s);
-    std::vector<double> hv(ns);
-    DBuf outv;
-    RLS_TRY(dalloc(outv, sizeof(double) * 3 * ns));
-    double* o_true = outv.as<double>();
+    double* o_true = w.outv.as<double>();
     double* o_res = o_true + ns;
     double* o_sem = o_true + 2 * ns;
     launch_sumsq_slots(q, n, ns, part, s);

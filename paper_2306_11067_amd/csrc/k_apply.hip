@@ -1,51 +1,151 @@
 // Level operator K_k(lambda) v = (G_h (x) G_v) v + lambda^2 S_k v, batched
-// over lambda, with fused prologue (how v is formed) and epilogue (what is
-// done with K v).  One workgroup computes a TILE_Y x TILE_X output tile of
-// one lambda slot:
-//   1. load v on the tile plus a halo of max(bw, 1) into LDS (index map of
-//      the Gram band supplies wrap / reflection / zero outside the grid);
-//   2. vertical pass of G_v over the tile rows for every loaded column;
+// over lambda, with a fused prologue (how v is formed while it is loaded)
+// and epilogue (what is done with K v).  One workgroup computes one output
+// tile of one lambda slot:
+//   1. load v on the tile plus a halo into LDS (the Gram band's index map
+//      supplies wrap / reflection / zero outside the grid), applying the
+//      prologue at every loaded point; stage the band coefficients in LDS;
+//   2. vertical pass of G_v for every loaded column;
 //   3. horizontal pass of G_h;
-//   4. add lambda^2 times the 9-point stencil S_k from the LDS tile;
+//   4. add lambda^2 times the 9-point stencil S_k read from the LDS tile;
 //   5. epilogue.
-// This is the "two-stage" level product of the paper's Section 3.2: for the
-// blur the products with A_k and A_k^T collapse into the separable Gram, and
-// M_k^T M_k is the Galerkin stencil of L^T D^2 L.
+// This is the two-stage level product of the paper's Section 3.2: for the
+// blur the products with A_k and A_k^T collapse into the separable Gram
+// A_k^T A_k = G_h (x) G_v, and M_k^T M_k is the Galerkin stencil of
+// L^T D^2 L.  The prologues and epilogues fuse the surrounding steps of the
+// V-cycle (Algorithm 1) and of PCG into the same pass over the tile.
 #include "common.h"
+#include "pcg_ctl.h"
 
 namespace rls {
 
-__device__ __forceinline__ double band_coeff(const BandDev& b, int r, int k) {
-    return b.uniform ? b.taps[k + b.bw]
-                     : b.table[(size_t)r * (2 * b.bw + 1) + k + b.bw];
+__device__ __forceinline__ double diag_at(const LevelGeom& g, double l2,
+                                          int i, int j, int64_t p) {
+    return g.gv.diag[i] * g.gh.diag[j] + l2 * g.S.c[p];
 }
+
+// Coarse points contributing to fine point f and their weights (linear
+// interpolation, vertex-centred).
+__device__ __forceinline__ int interp_sources(int f, int nf, int periodic,
+                                              int* I, double* w) {
+    const int nc = nf >> 1;
+    if ((f & 1) == 0) { I[0] = f >> 1; w[0] = 1.0; return 1; }
+    const int c = f >> 1;
+    if (c + 1 < nc) { I[0] = c; I[1] = c + 1; w[0] = w[1] = 0.5; return 2; }
+    if (periodic) { I[0] = c; I[1] = 0; w[0] = w[1] = 0.5; return 2; }
+    I[0] = c; w[0] = 1.0; return 1;
+}
+
+// (P e)(fi, fj) for the coarse vector e of size (nf_v/2) x (nf_h/2).
+__device__ __forceinline__ double prolong_at(const double* __restrict__ e,
+                                             int fi, int fj, int nvf, int nhf,
+                                             int periodic) {
+    int Ii[2], Jj[2];
+    double wi[2], wj[2];
+    const int ni = interp_sources(fi, nvf, periodic, Ii, wi);
+    const int nj = interp_sources(fj, nhf, periodic, Jj, wj);
+    const int64_t nvc = nvf >> 1;
+    double s = 0.0;
+    for (int b = 0; b < nj; ++b) {
+        double cs = 0.0;
+        for (int a = 0; a < ni; ++a) cs += wi[a] * e[Ii[a] + nvc * Jj[b]];
+        s += wj[b] * cs;
+    }
+    return s;
+}
+
+struct TileShape {
+    int lo, hv, hh, RY, SY, CX, SO, RO, CO, SR, WV, WH, NCV, NCH;
+    __host__ __device__ TileShape(const LevelGeom& g, int ext) {
+        lo = ext;
+        hv = (g.gv.bw > 1 ? g.gv.bw : 1) + lo;
+        hh = (g.gh.bw > 1 ? g.gh.bw : 1) + lo;
+        RY = TILE_Y + 2 * hv;
+        SY = RY | 1;
+        CX = TILE_X + 2 * hh;
+        RO = TILE_Y + lo;          // output rows (incl. low extension)
+        CO = TILE_X + lo;
+        SO = RO | 1;
+        SR = RO | 1;
+        WV = 2 * g.gv.bw + 1;
+        WH = 2 * g.gh.bw + 1;
+        NCV = g.gv.uniform ? 1 : RO;   // staged coefficient rows
+        NCH = g.gh.uniform ? 1 : CO;
+    }
+    __host__ __device__ size_t lds_doubles(int restrict_) const {
+        return (size_t)CX * SY + (size_t)CX * SO +
+               (restrict_ ? (size_t)CO * SR : 0) + (size_t)NCV * WV +
+               (size_t)NCH * WH;
+    }
+};
 
 template <int PRO, int EPI>
 __global__ void __launch_bounds__(APPLY_THREADS) k_apply(ApplyArgs a) {
     extern __shared__ double lds[];
-    const int slot = blockIdx.z;
+    __shared__ double red[APPLY_THREADS];
+    constexpr int EXT = EPI == EPI_RESTRICT ? 1 : 0;
+    const int slot = a.slots ? a.slots[blockIdx.z] : (int)blockIdx.z;
     if (a.active && !a.active[slot]) return;
     const LevelGeom& g = a.g;
     const int nv = g.nv, nh = g.nh;
     const int64_t n = (int64_t)nv * nh;
     const int i0 = blockIdx.x * TILE_Y, j0 = blockIdx.y * TILE_X;
     const int bwv = g.gv.bw, bwh = g.gh.bw;
-    const int hv = bwv > 1 ? bwv : 1, hh = bwh > 1 ? bwh : 1;
-    const int RY = TILE_Y + 2 * hv;
-    const int SY = RY | 1;
-    const int CX = TILE_X + 2 * hh;
-    const int SO = TILE_Y + 1;
+    const TileShape T(g, EXT);
     double* vin = lds;
-    double* vt = lds + CX * SY;
-    const double* src = a.in + (size_t)slot * n;
+    double* vt = vin + T.CX * T.SY;
+    double* rs = vt + T.CX * T.SO;
+    double* cv = rs + (EXT ? T.CO * T.SR : 0);
+    double* ch = cv + T.NCV * T.WV;
+    const size_t so = (size_t)slot * n;
+    const double* src = a.in ? a.in + so : nullptr;
     const double l2 = a.lam2[slot];
-    double beta = 0.0;
-    if (PRO == PRO_PUPDATE) beta = a.beta[slot];
+    const int per = g.S.periodic;
 
-    // 1. load (with prologue)
-    for (int e = threadIdx.x; e < CX * RY; e += APPLY_THREADS) {
-        const int jj = e / RY, ii = e - jj * RY;
-        const int ui = i0 - hv + ii, uj = j0 - hh + jj;
+    // PCG scalars folded into this kernel; tile (0, 0) of a slot leads
+    const bool lead = blockIdx.x == 0 && blockIdx.y == 0;
+    double beta = 0.0, cj = 0.0;
+    if (PRO == PRO_PUPDATE) {
+        if (!pcg_beta<APPLY_THREADS>(a.st, a.active_w, slot, a.part_rz, a.nrz,
+                                     a.parity, lead, red, beta))
+            return;
+    }
+    if (a.gate) {
+        if (!pcg_gate<APPLY_THREADS>(a.st, a.active_w, slot, a.part_rr, a.nrr,
+                                     lead, red))
+            return;
+    }
+    if (PRO == PRO_JACOBI || PRO == PRO_PROLONG_JAC)
+        cj = a.cheb_first[(size_t)slot * a.cheb_stride + 1];
+
+    // 1. stage band coefficients, load v with prologue
+    for (int e = threadIdx.x; e < T.NCV * T.WV; e += APPLY_THREADS) {
+        const int r = e / T.WV, k = e - r * T.WV;
+        double c = 0.0;
+        if (g.gv.uniform) {
+            c = g.gv.taps[k];
+        } else {
+            int gi = i0 + r - T.lo;
+            if (gi < 0 && per) gi += nv;
+            if (gi >= 0 && gi < nv) c = g.gv.table[(size_t)gi * T.WV + k];
+        }
+        cv[e] = c;
+    }
+    for (int e = threadIdx.x; e < T.NCH * T.WH; e += APPLY_THREADS) {
+        const int c0 = e / T.WH, k = e - c0 * T.WH;
+        double c = 0.0;
+        if (g.gh.uniform) {
+            c = g.gh.taps[k];
+        } else {
+            int gj = j0 + c0 - T.lo;
+            if (gj < 0 && per) gj += nh;
+            if (gj >= 0 && gj < nh) c = g.gh.table[(size_t)gj * T.WH + k];
+        }
+        ch[e] = c;
+    }
+    for (int e = threadIdx.x; e < T.CX * T.RY; e += APPLY_THREADS) {
+        const int jj = e / T.RY, ii = e - jj * T.RY;
+        const int ui = i0 - T.hv + ii, uj = j0 - T.hh + jj;
         bool okv, okh;
         const int gi = map_index(ui, nv, g.gv.map, okv);
         const int gj = map_index(uj, nh, g.gh.map, okh);
@@ -54,44 +154,64 @@ __global__ void __launch_bounds__(APPLY_THREADS) k_apply(ApplyArgs a) {
             const int64_t p = gi + (int64_t)nv * gj;
             if (PRO == PRO_PLAIN) {
                 v = src[p];
-            } else {
-                const double po = beta == 0.0 ? 0.0 : a.pold[(size_t)slot * n + p];
+            } else if (PRO == PRO_PUPDATE) {
+                const double po = beta == 0.0 ? 0.0 : a.pold[so + p];
                 v = src[p] + beta * po;
-                const bool own = ii >= hv && ii < hv + TILE_Y && jj >= hh &&
-                                 jj < hh + TILE_X && ui < nv && uj < nh;
-                if (own) a.pnew[(size_t)slot * n + p] = v;
+                const bool own = ii >= T.hv && ii < T.hv + TILE_Y &&
+                                 jj >= T.hh && jj < T.hh + TILE_X && ui < nv &&
+                                 uj < nh;
+                if (own) a.pnew[so + p] = v;
+            } else if (PRO == PRO_JACOBI) {
+                v = cj * a.f[a.f_shared ? p : so + p] / diag_at(g, l2, gi, gj, p);
+            } else if (PRO == PRO_PROLONG) {
+                v = src[p] + prolong_at(a.ec + (size_t)slot * (n >> 2), gi, gj,
+                                        nv, nh, per);
+            } else {   // PRO_PROLONG_JAC
+                v = cj * a.f[a.f_shared ? p : so + p] / diag_at(g, l2, gi, gj, p) +
+                    prolong_at(a.ec + (size_t)slot * (n >> 2), gi, gj, nv, nh, per);
             }
         }
-        vin[jj * SY + ii] = v;
+        vin[jj * T.SY + ii] = v;
     }
     __syncthreads();
 
-    // 2. vertical pass: vt(ii, jj) = sum_k Gv(i0+ii, k) vin(ii+hv+k, jj)
-    for (int e = threadIdx.x; e < TILE_Y * CX; e += APPLY_THREADS) {
-        const int jj = e / TILE_Y, ii = e - jj * TILE_Y;
-        const int gi = i0 + ii;
+    // 2. vertical pass over output rows [-lo, TILE_Y) of every loaded column
+    for (int e = threadIdx.x; e < T.RO * T.CX; e += APPLY_THREADS) {
+        const int jj = e / T.RO, r = e - jj * T.RO;        // r = row + lo
+        const int gi = i0 + r - T.lo;
         double s = 0.0;
-        if (gi < nv) {
-            const double* col = vin + jj * SY + ii + hv;
-            for (int k = -bwv; k <= bwv; ++k) s += band_coeff(g.gv, gi, k) * col[k];
+        if (gi < nv && (gi >= 0 || per)) {
+            const double* col = vin + jj * T.SY + r - T.lo + T.hv - bwv;
+            const double* cf = cv + (g.gv.uniform ? 0 : r) * T.WV;
+#pragma unroll 4
+            for (int k = 0; k < T.WV; ++k) s += cf[k] * col[k];
         }
-        vt[jj * SO + ii] = s;
+        vt[jj * T.SO + r] = s;
     }
     __syncthreads();
 
     // 3.-5. horizontal pass, stencil, epilogue
     double dot = 0.0;
-    for (int e = threadIdx.x; e < TILE_Y * TILE_X; e += APPLY_THREADS) {
-        const int jo = e / TILE_Y, ii = e - jo * TILE_Y;
-        const int gi = i0 + ii, gj = j0 + jo;
-        if (gi >= nv || gj >= nh) continue;
+    for (int e = threadIdx.x; e < T.RO * T.CO; e += APPLY_THREADS) {
+        const int c = e / T.RO, r = e - c * T.RO;          // local + lo
+        int gi = i0 + r - T.lo, gj = j0 + c - T.lo;
+        const bool okr = gi < nv && (gi >= 0 || per);
+        const bool okc = gj < nh && (gj >= 0 || per);
+        if (!okr || !okc) {
+            if (EXT) rs[c * T.SR + r] = 0.0;
+            continue;
+        }
+        if (gi < 0) gi += nv;
+        if (gj < 0) gj += nh;
         double kv = 0.0;
-        for (int k = -bwh; k <= bwh; ++k)
-            kv += band_coeff(g.gh, gj, k) * vt[(jo + hh + k) * SO + ii];
-        // stencil
-        const double* vc = vin + (jo + hh) * SY + ii + hv;   // v(gi, gj)
+        {
+            const double* row = vt + (c - T.lo + T.hh - bwh) * T.SO + r;
+            const double* cf = ch + (g.gh.uniform ? 0 : c) * T.WH;
+#pragma unroll 4
+            for (int k = 0; k < T.WH; ++k) kv += cf[k] * row[k * T.SO];
+        }
+        const double* vc = vin + (c - T.lo + T.hh) * T.SY + r - T.lo + T.hv;
         const int64_t p = gi + (int64_t)nv * gj;
-        const int per = g.S.periodic;
         int im = gi - 1, jm = gj - 1, ip = gi + 1;
         const bool okim = wrap_or_drop(im, nv, per);
         const bool okjm = wrap_or_drop(jm, nh, per);
@@ -99,84 +219,139 @@ __global__ void __launch_bounds__(APPLY_THREADS) k_apply(ApplyArgs a) {
         double sv = g.S.c[p] * vc[0];
         sv += g.S.cn[p] * vc[1];
         if (okim) sv += g.S.cn[im + (int64_t)nv * gj] * vc[-1];
-        sv += g.S.ce[p] * vc[SY];
-        if (okjm) sv += g.S.ce[gi + (int64_t)nv * jm] * vc[-SY];
+        sv += g.S.ce[p] * vc[T.SY];
+        if (okjm) sv += g.S.ce[gi + (int64_t)nv * jm] * vc[-T.SY];
         if (g.S.nine) {
-            sv += g.S.cne[p] * vc[SY + 1];
-            if (okim && okjm) sv += g.S.cne[im + (int64_t)nv * jm] * vc[-SY - 1];
-            sv += g.S.cse[p] * vc[SY - 1];
-            if (okip && okjm) sv += g.S.cse[ip + (int64_t)nv * jm] * vc[-SY + 1];
+            sv += g.S.cne[p] * vc[T.SY + 1];
+            if (okim && okjm) sv += g.S.cne[im + (int64_t)nv * jm] * vc[-T.SY - 1];
+            sv += g.S.cse[p] * vc[T.SY - 1];
+            if (okip && okjm) sv += g.S.cse[ip + (int64_t)nv * jm] * vc[-T.SY + 1];
         }
         kv += l2 * sv;
         const double v = vc[0];
-        const size_t o = (size_t)slot * n + p;
+        const size_t o = so + p;
         if (EPI == EPI_STORE) {
             a.out[o] = kv;
         } else if (EPI == EPI_DOT) {
             a.out[o] = kv;
             dot += v * kv;
         } else if (EPI == EPI_RESID) {
-            const double f = a.f[a.f_shared ? p : o];
-            a.out[o] = f - kv;
+            a.out[o] = a.f[a.f_shared ? p : o] - kv;
+        } else if (EPI == EPI_RESTRICT) {
+            rs[c * T.SR + r] = a.f[a.f_shared ? p : o] - kv;
         } else {   // EPI_CHEB
             const double f = a.f[a.f_shared ? p : o];
-            const double dg = g.gv.diag[gi] * g.gh.diag[gj] + l2 * g.S.c[p];
             const double* cc = a.cheb + (size_t)slot * a.cheb_stride;
-            const double dn = cc[0] * a.d[o] + cc[1] * (f - kv) / dg;
+            const double dprev = PRO == PRO_JACOBI ? v : a.d[o];
+            const double dn = cc[0] * dprev + cc[1] * (f - kv) / diag_at(g, l2, gi, gj, p);
             a.d[o] = dn;
-            a.out[o] = v + dn;
+            const double xn = v + dn;
+            a.out[o] = xn;
+            if (a.dot) dot += f * xn;
         }
     }
-    if (EPI == EPI_DOT) {
-        __shared__ double sh[APPLY_THREADS];
-        const double s = block_sum<APPLY_THREADS>(dot, sh);
+    if (EPI == EPI_RESTRICT) {
+        // full weighting of the residual tile onto the coarse points whose
+        // centre lies in the tile: fc(I, J) = sum P(f, (I, J)) res(f)
+        __syncthreads();
+        const int nvc = nv >> 1, nhc = nh >> 1;
+        const int I0 = i0 >> 1, J0 = j0 >> 1;
+        constexpr int CI = TILE_Y / 2, CJ = TILE_X / 2;
+        for (int e = threadIdx.x; e < CI * CJ; e += APPLY_THREADS) {
+            const int cjj = e / CI, cii = e - cjj * CI;
+            const int I = I0 + cii, J = J0 + cjj;
+            if (I >= nvc || J >= nhc) continue;
+            double s = 0.0;
+            for (int b = -1; b <= 1; ++b) {
+                int fj = 2 * J + b;
+                if (!wrap_or_drop(fj, nh, per)) continue;
+                const double wj = interp_weight(fj, J, nh, per);
+                if (wj == 0.0) continue;
+                const int lc = 2 * cjj + b + 1;             // local column + lo
+                double cs = 0.0;
+                for (int a2 = -1; a2 <= 1; ++a2) {
+                    int fi = 2 * I + a2;
+                    if (!wrap_or_drop(fi, nv, per)) continue;
+                    const double wi = interp_weight(fi, I, nv, per);
+                    if (wi != 0.0) cs += wi * rs[lc * T.SR + 2 * cii + a2 + 1];
+                }
+                s += wj * cs;
+            }
+            a.fc[(size_t)slot * nvc * nhc + I + (int64_t)nvc * J] = s;
+        }
+    }
+    if (EPI == EPI_DOT || (EPI == EPI_CHEB && a.dot)) {
+        const double s = block_sum<APPLY_THREADS>(dot, red);
         if (threadIdx.x == 0)
-            a.part[(size_t)slot * gridDim.x * gridDim.y + blockIdx.x +
+            a.part[(size_t)slot * a.part_stride + blockIdx.x +
                    (size_t)gridDim.x * blockIdx.y] = s;
     }
 }
 
-static size_t apply_lds_bytes(const LevelGeom& g) {
-    const int hv = g.gv.bw > 1 ? g.gv.bw : 1, hh = g.gh.bw > 1 ? g.gh.bw : 1;
-    const int SY = (TILE_Y + 2 * hv) | 1;
-    const int CX = TILE_X + 2 * hh;
-    return sizeof(double) * (size_t)CX * (SY + TILE_Y + 1);
+template <int PRO, int EPI>
+static void configure_t() {
+    // dynamic LDS may use what the kernel's static LDS leaves of 160 KiB
+    hipFuncAttributes attr;
+    size_t stat = 0;
+    if (hipFuncGetAttributes(&attr, (const void*)k_apply<PRO, EPI>) == hipSuccess)
+        stat = attr.sharedSizeBytes;
+    hipFuncSetAttribute((const void*)k_apply<PRO, EPI>,
+                        hipFuncAttributeMaxDynamicSharedMemorySize,
+                        (int)(160 * 1024 - stat));
+}
+
+void configure_apply_kernels() {
+    static bool done = false;
+    if (done) return;
+    configure_t<PRO_PUPDATE, EPI_DOT>();
+    configure_t<PRO_JACOBI, EPI_CHEB>();
+    configure_t<PRO_JACOBI, EPI_RESTRICT>();
+    configure_t<PRO_PROLONG, EPI_CHEB>();
+    configure_t<PRO_PROLONG_JAC, EPI_CHEB>();
+    configure_t<PRO_PLAIN, EPI_STORE>();
+    configure_t<PRO_PLAIN, EPI_DOT>();
+    configure_t<PRO_PLAIN, EPI_RESID>();
+    configure_t<PRO_PLAIN, EPI_RESTRICT>();
+    configure_t<PRO_PLAIN, EPI_CHEB>();
+    hipGetLastError();
+    done = true;
 }
 
 template <int PRO, int EPI>
 static void launch_t(const ApplyArgs& a, hipStream_t s) {
-    static bool configured = false;
-    if (!configured) {
-        // dynamic LDS may use what the kernel's static LDS leaves of 160 KiB
-        hipFuncAttributes attr;
-        size_t stat = 0;
-        if (hipFuncGetAttributes(&attr, (const void*)k_apply<PRO, EPI>) ==
-            hipSuccess)
-            stat = attr.sharedSizeBytes;
-        hipFuncSetAttribute((const void*)k_apply<PRO, EPI>,
-                            hipFuncAttributeMaxDynamicSharedMemorySize,
-                            (int)(160 * 1024 - stat));
-        configured = true;
-    }
+    const TileShape T(a.g, EPI == EPI_RESTRICT);
     dim3 grid((a.g.nv + TILE_Y - 1) / TILE_Y, (a.g.nh + TILE_X - 1) / TILE_X,
               a.nslot);
     hipLaunchKernelGGL((k_apply<PRO, EPI>), grid, dim3(APPLY_THREADS),
-                       apply_lds_bytes(a.g), s, a);
+                       sizeof(double) * T.lds_doubles(EPI == EPI_RESTRICT), s,
+                       a);
 }
 
 int apply_tiles(const LevelGeom& g) {
     return ((g.nv + TILE_Y - 1) / TILE_Y) * ((g.nh + TILE_X - 1) / TILE_X);
 }
 
+size_t apply_lds_bytes(const LevelGeom& g, int epi) {
+    const TileShape T(g, epi == EPI_RESTRICT);
+    return sizeof(double) * T.lds_doubles(epi == EPI_RESTRICT);
+}
+
 void launch_apply(int pro, int epi, const ApplyArgs& a, hipStream_t s) {
-    if (pro == PRO_PUPDATE) {
-        launch_t<PRO_PUPDATE, EPI_DOT>(a, s);
-        return;
+    switch (pro) {
+        case PRO_PUPDATE: launch_t<PRO_PUPDATE, EPI_DOT>(a, s); return;
+        case PRO_JACOBI:
+            if (epi == EPI_RESTRICT) launch_t<PRO_JACOBI, EPI_RESTRICT>(a, s);
+            else launch_t<PRO_JACOBI, EPI_CHEB>(a, s);
+            return;
+        case PRO_PROLONG: launch_t<PRO_PROLONG, EPI_CHEB>(a, s); return;
+        case PRO_PROLONG_JAC: launch_t<PRO_PROLONG_JAC, EPI_CHEB>(a, s); return;
+        default: break;
     }
     switch (epi) {
         case EPI_STORE: launch_t<PRO_PLAIN, EPI_STORE>(a, s); break;
         case EPI_DOT: launch_t<PRO_PLAIN, EPI_DOT>(a, s); break;
         case EPI_RESID: launch_t<PRO_PLAIN, EPI_RESID>(a, s); break;
+        case EPI_RESTRICT: launch_t<PRO_PLAIN, EPI_RESTRICT>(a, s); break;
         default: launch_t<PRO_PLAIN, EPI_CHEB>(a, s); break;
     }
 }

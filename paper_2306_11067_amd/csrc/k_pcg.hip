@@ -5,6 +5,7 @@
 #include <cmath>
 
 #include "common.h"
+#include "pcg_ctl.h"
 
 namespace rls {
 
@@ -34,9 +35,10 @@ __global__ void k_axpy_sub(const double* __restrict__ f, int f_shared,
 
 __global__ void __launch_bounds__(VB)
 k_dot(const double* __restrict__ a, const double* __restrict__ b, int64_t n,
-      const int* __restrict__ active, double* __restrict__ part) {
+      const int* __restrict__ slots, const int* __restrict__ active,
+      double* __restrict__ part) {
     __shared__ double sh[VB];
-    const int slot = blockIdx.y;
+    const int slot = slots ? slots[blockIdx.y] : (int)blockIdx.y;
     if (active && !active[slot]) return;
     const size_t base = (size_t)slot * n;
     double s = 0.0;
@@ -118,15 +120,22 @@ k_weighted_grad_sq(const double* __restrict__ x, const double* __restrict__ d,
     if (threadIdx.x == 0) part[(size_t)slot * gridDim.x + blockIdx.x] = s;
 }
 
-// x += alpha p ; r -= alpha q ; partial ||r||^2
+// alpha = gamma / (p . q) (folded finalization); x += alpha p ;
+// r -= alpha q ; partial ||r||^2
 __global__ void __launch_bounds__(VB)
-k_update_xr(const SlotState* __restrict__ st, int64_t n, double* __restrict__ x,
+k_update_xr(SlotState* __restrict__ st, int* __restrict__ active,
+            const int* __restrict__ slots, int64_t n, double* __restrict__ x,
             double* __restrict__ r, const double* __restrict__ p,
-            const double* __restrict__ q, double* __restrict__ part) {
+            const double* __restrict__ q, const double* __restrict__ part_pq,
+            int npq, int parity, double* __restrict__ part) {
     __shared__ double sh[VB];
-    const int slot = blockIdx.y;
-    if (!st[slot].active) return;
-    const double al = st[slot].alpha;
+    const int slot = slots ? slots[blockIdx.y] : (int)blockIdx.y;
+    if (!active[slot]) return;
+    double al;
+    // block 0 of the slot's row of blocks leads
+    if (!pcg_alpha<VB>(st, active, slot, part_pq, npq, parity, blockIdx.x == 0,
+                       sh, al))
+        return;
     const size_t base = (size_t)slot * n;
     double s = 0.0;
     const int64_t p0 = (int64_t)blockIdx.x * VCHUNK + threadIdx.x;
@@ -152,108 +161,30 @@ __device__ double slot_sum(const double* part, int nparts, double* sh) {
 
 __global__ void __launch_bounds__(VB)
 k_pcg_init(SlotState* __restrict__ st, const double* __restrict__ fparts,
-           int nf, const double* __restrict__ rparts, int nr,
-           const double* __restrict__ gparts, int ng, double tol, int absolute,
-           int maxit, int* __restrict__ active) {
+           int nf, const double* __restrict__ rparts, int nr, double tol,
+           int absolute, int maxit, int* __restrict__ active) {
     __shared__ double sh[VB];
     const int slot = blockIdx.x;
     const double ff = slot_sum(fparts, nf, sh);
     const double rr = slot_sum(rparts + (size_t)slot * nr, nr, sh);
-    const double gg = slot_sum(gparts + (size_t)slot * ng, ng, sh);
     if (threadIdx.x == 0) {
         SlotState& s = st[slot];
         s.fnorm = sqrt(ff);
         s.target = absolute ? tol : tol * s.fnorm;
         s.rr = rr;
-        s.gamma = gg;
+        s.gam[0] = s.gam[1] = 0.0;
         s.alpha = 0.0;
-        s.beta = 0.0;
         s.it = 0;
         s.maxit = maxit;
         s.flags = 0;
         s.active = 1;
-        if (!isfinite(rr) || !isfinite(gg)) {
-            s.flags |= RLS_FLAG_NONFINITE;
-            s.active = 0;
-        } else if (sqrt(rr) <= s.target) {
-            s.flags |= RLS_FLAG_CONVERGED;
-            s.active = 0;
-        } else if (!(gg > 0.0)) {
-            s.flags |= RLS_FLAG_BREAKDOWN;
-            s.active = 0;
-        }
-        active[slot] = s.active;
-    }
-}
-
-__global__ void __launch_bounds__(VB)
-k_finalize_alpha(SlotState* __restrict__ st, const double* __restrict__ part,
-                 int nparts, int* __restrict__ active) {
-    __shared__ double sh[VB];
-    const int slot = blockIdx.x;
-    if (!st[slot].active) return;
-    const double pq = slot_sum(part + (size_t)slot * nparts, nparts, sh);
-    if (threadIdx.x == 0) {
-        SlotState& s = st[slot];
-        if (!isfinite(pq)) {
-            s.flags |= RLS_FLAG_NONFINITE;
-            s.active = 0;
-        } else if (!(pq > 0.0)) {
-            s.flags |= RLS_FLAG_BREAKDOWN;
-            s.active = 0;
-        } else {
-            s.alpha = s.gamma / pq;
-        }
-        active[slot] = s.active;
-    }
-}
-
-__global__ void __launch_bounds__(VB)
-k_finalize_rr(SlotState* __restrict__ st, const double* __restrict__ part,
-              int nparts, int* __restrict__ active) {
-    __shared__ double sh[VB];
-    const int slot = blockIdx.x;
-    if (!st[slot].active) return;
-    const double rr = slot_sum(part + (size_t)slot * nparts, nparts, sh);
-    if (threadIdx.x == 0) {
-        SlotState& s = st[slot];
-        s.rr = rr;
-        s.it += 1;
         if (!isfinite(rr)) {
             s.flags |= RLS_FLAG_NONFINITE;
             s.active = 0;
         } else if (sqrt(rr) <= s.target) {
             s.flags |= RLS_FLAG_CONVERGED;
             s.active = 0;
-        } else if (s.it >= s.maxit) {
-            s.flags |= RLS_FLAG_MAXIT;
-            s.active = 0;
         }
-        active[slot] = s.active;
-    }
-}
-
-__global__ void __launch_bounds__(VB)
-k_finalize_beta(SlotState* __restrict__ st, const double* __restrict__ part,
-                int nparts, double* __restrict__ beta,
-                int* __restrict__ active) {
-    __shared__ double sh[VB];
-    const int slot = blockIdx.x;
-    if (!st[slot].active) return;
-    const double g = slot_sum(part + (size_t)slot * nparts, nparts, sh);
-    if (threadIdx.x == 0) {
-        SlotState& s = st[slot];
-        if (!isfinite(g)) {
-            s.flags |= RLS_FLAG_NONFINITE;
-            s.active = 0;
-        } else if (!(g > 0.0)) {
-            s.flags |= RLS_FLAG_BREAKDOWN;
-            s.active = 0;
-        } else {
-            s.beta = g / s.gamma;
-            s.gamma = g;
-        }
-        beta[slot] = s.beta;
         active[slot] = s.active;
     }
 }
@@ -280,9 +211,10 @@ void launch_axpy_sub(const double* f, int f_shared, const double* kx,
                        f, f_shared, kx, n, r);
 }
 void launch_dot(const double* a, const double* b, int64_t n, int nslot,
-                const int* active, double* part, hipStream_t s) {
+                const int* slots, const int* active, double* part,
+                hipStream_t s) {
     hipLaunchKernelGGL(k_dot, dim3(vec_blocks(n), nslot), dim3(VB), 0, s, a, b,
-                       n, active, part);
+                       n, slots, active, part);
 }
 void launch_sumsq_slots(const double* a, int64_t n, int nslot, double* part,
                         hipStream_t s) {
@@ -301,34 +233,19 @@ void launch_weighted_grad_sq(const double* x, const double* d, int nv, int nh,
                        dim3(vec_blocks((int64_t)nv * nh), nslot), dim3(VB), 0,
                        s, x, d, nv, nh, periodic, part);
 }
-void launch_update_xr(const SlotState* st, int64_t n, int nslot, double* x,
-                      double* r, const double* p, const double* q,
-                      double* part, hipStream_t s) {
+void launch_update_xr(SlotState* st, int* active, const int* slots,
+                      int64_t n, int nslot, double* x, double* r,
+                      const double* p, const double* q, const double* part_pq,
+                      int npq, int parity, double* part_rr, hipStream_t s) {
     hipLaunchKernelGGL(k_update_xr, dim3(vec_blocks(n), nslot), dim3(VB), 0, s,
-                       st, n, x, r, p, q, part);
+                       st, active, slots, n, x, r, p, q, part_pq, npq, parity,
+                       part_rr);
 }
 void launch_pcg_init(SlotState* st, int nslot, const double* fparts, int nf,
-                     const double* rparts, int nr, const double* gparts,
-                     int ng, double tol, int absolute, int maxit, int* active,
-                     hipStream_t s) {
+                     const double* rparts, int nr, double tol, int absolute,
+                     int maxit, int* active, hipStream_t s) {
     hipLaunchKernelGGL(k_pcg_init, dim3(nslot), dim3(VB), 0, s, st, fparts, nf,
-                       rparts, nr, gparts, ng, tol, absolute, maxit, active);
-}
-void launch_finalize_alpha(SlotState* st, int nslot, const double* part,
-                           int nparts, int* active, hipStream_t s) {
-    hipLaunchKernelGGL(k_finalize_alpha, dim3(nslot), dim3(VB), 0, s, st, part,
-                       nparts, active);
-}
-void launch_finalize_rr(SlotState* st, int nslot, const double* part,
-                        int nparts, int* active, hipStream_t s) {
-    hipLaunchKernelGGL(k_finalize_rr, dim3(nslot), dim3(VB), 0, s, st, part,
-                       nparts, active);
-}
-void launch_finalize_beta(SlotState* st, int nslot, const double* part,
-                          int nparts, double* beta, int* active,
-                          hipStream_t s) {
-    hipLaunchKernelGGL(k_finalize_beta, dim3(nslot), dim3(VB), 0, s, st, part,
-                       nparts, beta, active);
+                       rparts, nr, tol, absolute, maxit, active);
 }
 void launch_reduce_slots(const double* part, int nparts, int nslot,
                          double* out, hipStream_t s) {

@@ -7,11 +7,12 @@ namespace rls {
 
 // x = c2 f / diag(K), d = x: the first Chebyshev step from x = 0.
 __global__ void k_jacobi_init(LevelGeom g, const double* __restrict__ lam2,
+                              const int* __restrict__ slots,
                               const int* __restrict__ active,
                               const double* __restrict__ f, int f_shared,
                               const double* __restrict__ cheb, int cheb_stride,
                               double* __restrict__ x, double* __restrict__ d) {
-    const int slot = blockIdx.y;
+    const int slot = slots ? slots[blockIdx.y] : (int)blockIdx.y;
     if (active && !active[slot]) return;
     const int64_t n = (int64_t)g.nv * g.nh;
     const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -56,7 +57,7 @@ __global__ void k_restrict(int nvf, int nhf, int periodic,
 }
 
 // Coarse points contributing to fine point f (at most two) and weights.
-__device__ __forceinline__ int interp_sources(int f, int nf, int periodic,
+__device__ __forceinline__ int interp_sources_v(int f, int nf, int periodic,
                                               int* I, double* w) {
     const int nc = nf >> 1;
     if ((f & 1) == 0) { I[0] = f >> 1; w[0] = 1.0; return 1; }
@@ -80,8 +81,8 @@ __global__ void k_prolong_add(int nvf, int nhf, int periodic,
     const int fi = (int)(p % nvf), fj = (int)(p / nvf);
     int Ii[2], Jj[2];
     double wi[2], wj[2];
-    const int ni = interp_sources(fi, nvf, periodic, Ii, wi);
-    const int nj = interp_sources(fj, nhf, periodic, Jj, wj);
+    const int ni = interp_sources_v(fi, nvf, periodic, Ii, wi);
+    const int nj = interp_sources_v(fj, nhf, periodic, Jj, wj);
     const double* e = ec + (size_t)slot * nc;
     double s = 0.0;
     for (int b = 0; b < nj; ++b) {
@@ -96,10 +97,10 @@ __global__ void k_prolong_add(int nvf, int nhf, int periodic,
 // W row-major at Winv[slot], W^T (row-major) right after it.
 __global__ void __launch_bounds__(1024)
 k_coarse_solve(const double* __restrict__ Wall, int n,
-               const int* __restrict__ active, const double* __restrict__ f,
-               double* __restrict__ z) {
+               const int* __restrict__ slots, const int* __restrict__ active,
+               const double* __restrict__ f, double* __restrict__ z) {
     extern __shared__ double sh[];
-    const int slot = blockIdx.x;
+    const int slot = slots ? slots[blockIdx.x] : (int)blockIdx.x;
     if (active && !active[slot]) return;
     const double* W = Wall + (size_t)slot * 2 * n * n;
     const double* Wt = W + (size_t)n * n;   // Wt[c*n + i] = W(i, c)
@@ -125,12 +126,13 @@ k_coarse_solve(const double* __restrict__ Wall, int n,
 static inline int nblk(int64_t n, int b) { return (int)((n + b - 1) / b); }
 
 void launch_jacobi_init(const LevelGeom& g, int nslot, const double* lam2,
-                        const int* active, const double* f, int f_shared,
-                        const double* cheb, int cheb_stride, double* x,
-                        double* d, hipStream_t s) {
+                        const int* slots, const int* active, const double* f,
+                        int f_shared, const double* cheb, int cheb_stride,
+                        double* x, double* d, hipStream_t s) {
     const int64_t n = (int64_t)g.nv * g.nh;
     hipLaunchKernelGGL(k_jacobi_init, dim3(nblk(n, 256), nslot), dim3(256), 0,
-                       s, g, lam2, active, f, f_shared, cheb, cheb_stride, x, d);
+                       s, g, lam2, slots, active, f, f_shared, cheb, cheb_stride,
+                       x, d);
 }
 
 void launch_restrict(const LevelGeom& fine, const LevelGeom& coarse, int nslot,
@@ -151,11 +153,11 @@ void launch_prolong_add(const LevelGeom& fine, const LevelGeom& coarse,
 }
 
 void launch_coarse_solve(const double* Wall, int n, int nslot,
-                         const int* active, const double* f, double* z,
-                         hipStream_t s) {
+                         const int* slots, const int* active, const double* f,
+                         double* z, hipStream_t s) {
     const int threads = n >= 1024 ? 1024 : ((n + 63) / 64) * 64;
     hipLaunchKernelGGL(k_coarse_solve, dim3(nslot), dim3(threads),
-                       2 * n * sizeof(double), s, Wall, n, active, f, z);
+                       2 * n * sizeof(double), s, Wall, n, slots, active, f, z);
 }
 
 }  // namespace rls

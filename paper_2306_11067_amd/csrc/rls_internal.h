@@ -51,40 +51,75 @@ struct LevelGeom {
 // Tile of the level-operator kernel (i is the contiguous axis).
 constexpr int TILE_Y = 64;
 constexpr int TILE_X = 16;
-constexpr int APPLY_THREADS = 256;
+constexpr int APPLY_THREADS = 1024;
 
 // Prologue: how the operand v of K v is formed while loading a tile.
 enum Prologue : int {
-    PRO_PLAIN = 0,   // v = in
-    PRO_PUPDATE = 1  // v = z + beta * p_old ; p_new = v (interior)
+    PRO_PLAIN = 0,    // v = in
+    PRO_PUPDATE = 1,  // v = z + beta * p_old ; p_new = v (interior)
+    PRO_JACOBI = 2,   // v = c2 f / diag(K): first Chebyshev step from zero
+    PRO_PROLONG = 3,  // v = in + P e_coarse: coarse-grid correction
+    PRO_PROLONG_JAC = 4  // v = c2 f / diag(K) + P e_coarse (nu = 1)
 };
 // Epilogue: what is done with (v, K v) at each output point.
 enum Epilogue : int {
-    EPI_STORE = 0,   // out = K v
-    EPI_DOT = 1,     // out = K v ; partial sum of v . K v
-    EPI_RESID = 2,   // out = f - K v
-    EPI_CHEB = 3     // res = f - K v ; d = c1 d + c2 res / diag ; out = v + d
+    EPI_STORE = 0,    // out = K v
+    EPI_DOT = 1,      // out = K v ; partial sum of v . K v
+    EPI_RESID = 2,    // out = f - K v
+    EPI_CHEB = 3,     // d = c1 d + c2 (f - K v) / diag ; out = v + d
+                      //   (optional partial sum of f . out)
+    EPI_RESTRICT = 4  // fc = P^T (f - K v) on the coarse grid
+};
+
+struct SlotState {
+    double gam[2];  // r . z of the last two iterations (double-buffered so
+                    // that one kernel can read the old value while its
+                    // leader writes the new one)
+    double alpha;
+    double rr;      // ||r||^2
+    double target;  // residual norm target
+    double fnorm;   // ||A^T b||
+    int it;         // completed iterations
+    int active;
+    int flags;
+    int maxit;
 };
 
 struct ApplyArgs {
     LevelGeom g;
-    int nslot = 0;
+    int nslot = 0;                   // grid z: number of slots launched
+    const int* slots = nullptr;      // slot of each grid z (null: identity)
     const double* lam2 = nullptr;    // per slot lambda^2
     const int* active = nullptr;     // per slot, may be null (all active)
-    const double* in = nullptr;      // v (or z for PRO_PUPDATE), slot stride n
+    const double* in = nullptr;      // v, z (PUPDATE) or x (PROLONG)
     const double* pold = nullptr;    // PRO_PUPDATE
     double* pnew = nullptr;          // PRO_PUPDATE
     const double* beta = nullptr;    // PRO_PUPDATE, per slot
+    const double* ec = nullptr;      // PRO_PROLONG coarse correction
     double* out = nullptr;
-    const double* f = nullptr;       // EPI_RESID / EPI_CHEB right-hand side
+    const double* f = nullptr;       // right-hand side (RESID/CHEB/RESTRICT/JACOBI)
     int f_shared = 0;                // f has one vector for all slots
     double* d = nullptr;             // EPI_CHEB direction, in place
-    const double* cheb = nullptr;    // EPI_CHEB per slot (c1, c2) pairs
+    const double* cheb = nullptr;    // per slot (c1, c2) of this step
+    const double* cheb_first = nullptr;  // PRO_JACOBI: (c1, c2) of step 0
     int cheb_stride = 0;             // doubles between slots in cheb
-    double* part = nullptr;          // EPI_DOT partials [slot][tile]
+    double* fc = nullptr;            // EPI_RESTRICT coarse right-hand side
+    int dot = 0;                     // EPI_CHEB: accumulate f . out
+    double* part = nullptr;          // partial sums [slot][tile]
+    int part_stride = 0;             // tiles per slot in part
+    // PCG control folded into the kernels (see k_pcg.hip):
+    SlotState* st = nullptr;
+    int* active_w = nullptr;         // writable copy of `active` (leaders)
+    const double* part_rz = nullptr; // PRO_PUPDATE: partials of r . z
+    int nrz = 0;
+    int parity = 0;                  // iteration parity (gam double buffer)
+    int gate = 0;                    // convergence test before the V-cycle
+    const double* part_rr = nullptr; // gate: partials of ||r||^2
+    int nrr = 0;
 };
 
 void launch_apply(int pro, int epi, const ApplyArgs& a, hipStream_t s);
+void configure_apply_kernels();  // LDS limits of every variant, once
 
 // ---- setup kernels (k_setup.hip) ------------------------------------
 void launch_blur_band(const double* taps, int r, int n, int bc, double* band,
@@ -116,9 +151,9 @@ void launch_check_weights(const double* d, int64_t n, int* bad,
 
 // ---- vector / multigrid kernels (k_vec.hip) -------------------------
 void launch_jacobi_init(const LevelGeom& g, int nslot, const double* lam2,
-                        const int* active, const double* f, int f_shared,
-                        const double* cheb, int cheb_stride, double* x,
-                        double* d, hipStream_t s);
+                        const int* slots, const int* active, const double* f,
+                        int f_shared, const double* cheb, int cheb_stride,
+                        double* x, double* d, hipStream_t s);
 void launch_restrict(const LevelGeom& fine, const LevelGeom& coarse, int nslot,
                      const int* active, const double* res, double* fc,
                      hipStream_t s);
@@ -126,22 +161,10 @@ void launch_prolong_add(const LevelGeom& fine, const LevelGeom& coarse,
                         int nslot, const int* active, const double* ec,
                         double* x, hipStream_t s);
 void launch_coarse_solve(const double* Kinv, int n, int nslot,
-                         const int* active, const double* f, double* z,
-                         hipStream_t s);
+                         const int* slots, const int* active, const double* f,
+                         double* z, hipStream_t s);
 
 // ---- PCG kernels (k_pcg.hip) ------------------------------------------
-struct SlotState {
-    double gamma;   // r . z
-    double alpha;
-    double beta;
-    double rr;      // ||r||^2
-    double target;  // residual norm target
-    double fnorm;   // ||A^T b||
-    int it;
-    int active;
-    int flags;
-    int maxit;
-};
 
 int vec_blocks(int64_t n);  // partial-sum slots per vector
 void launch_broadcast(const double* src, int64_t n, int nslot, double* dst,
@@ -149,21 +172,15 @@ void launch_broadcast(const double* src, int64_t n, int nslot, double* dst,
 void launch_axpy_sub(const double* f, int f_shared, const double* kx,
                      int64_t n, int nslot, double* r, hipStream_t s);
 void launch_dot(const double* a, const double* b, int64_t n, int nslot,
-                const int* active, double* part, hipStream_t s);
-void launch_update_xr(const SlotState* st, int64_t n, int nslot, double* x,
-                      double* r, const double* p, const double* q,
-                      double* part, hipStream_t s);
+                const int* slots, const int* active, double* part,
+                hipStream_t s);
+void launch_update_xr(SlotState* st, int* active, const int* slots,
+                      int64_t n, int nslot, double* x, double* r,
+                      const double* p, const double* q, const double* part_pq,
+                      int npq, int parity, double* part_rr, hipStream_t s);
 void launch_pcg_init(SlotState* st, int nslot, const double* fparts, int nf,
-                     const double* rparts, int nr, const double* gparts,
-                     int ng, double tol, int absolute, int maxit, int* active,
-                     hipStream_t s);
-void launch_finalize_alpha(SlotState* st, int nslot, const double* part,
-                           int nparts, int* active, hipStream_t s);
-void launch_finalize_rr(SlotState* st, int nslot, const double* part,
-                        int nparts, int* active, hipStream_t s);
-void launch_finalize_beta(SlotState* st, int nslot, const double* part,
-                          int nparts, double* beta, int* active,
-                          hipStream_t s);
+                     const double* rparts, int nr, double tol, int absolute,
+                     int maxit, int* active, hipStream_t s);
 void launch_sumsq_slots(const double* a, int64_t n, int nslot, double* part,
                         hipStream_t s);
 void launch_reduce_slots(const double* part, int nparts, int nslot,
@@ -175,5 +192,40 @@ void launch_sub_sumsq(const double* a, const double* b, int64_t n, int nslot,
                       double* part, hipStream_t s);
 
 int apply_tiles(const LevelGeom& g);
+
+// ---- coarse tail (k_tail.hip) -----------------------------------------
+constexpr int TAIL_MAX_POINTS = 1024;   // levels this small run in the tail
+constexpr int TAIL_MAX_LEVELS = 8;
+
+struct TailLevel {
+    int nv = 0, nh = 0;
+    BandDev gv, gh;                  // band tables are always present
+    StencilDev S;
+    const double* cheb = nullptr;    // per slot Chebyshev (c1, c2) pairs
+};
+
+struct TailArgs {
+    int nlev = 0;                    // tail levels, the last is the coarsest
+    TailLevel lev[TAIL_MAX_LEVELS];
+    int nu = 2, cheb_stride = 0, periodic = 0;
+    const double* lam2 = nullptr;
+    const int* slots = nullptr;
+    const int* active = nullptr;
+    const double* f = nullptr;       // right-hand side on the first tail level
+    double* z = nullptr;             // result on the first tail level
+    const double* W = nullptr;       // coarsest W = L^{-1} and W^T per slot
+    int dot = 0;                     // write partials of f . z (level 0)
+    double* part = nullptr;
+    int part_stride = 0;
+    int gate = 0;                    // convergence test first (level 0)
+    SlotState* st = nullptr;
+    int* active_w = nullptr;
+    const double* part_rr = nullptr;
+    int nrr = 0;
+};
+
+void launch_tail(const TailArgs& a, int nslot, hipStream_t s);
+size_t tail_lds_bytes(const TailArgs& a);
+size_t apply_lds_bytes(const LevelGeom& g, int epi);
 
 }  // namespace rls

@@ -126,3 +126,19 @@ def test_error_paths():
     bad[5] = np.nan
     with pytest.raises(RLSError):
         prob.set_weights(dev(bad))
+
+
+def test_graph_replay_equals_direct_launches():
+    # The same sweep with iteration chunks replayed as HIP graphs and with
+    # kernels launched one by one gives bitwise identical results, twice.
+    P_ = W.small_deblur(96, 64, 3, 1.5, "reflective", "neumann", 3, nlam=5)
+    prob = _problem(P_, 1)
+    b = dev(P_.b)
+    xd, rd, sd, idd = prob.solve_sweep(b, P_.lams, 1e-11, graph=False,
+                                       poll_every=6)
+    for _ in range(2):
+        xg, rg, sg, ig = prob.solve_sweep(b, P_.lams, 1e-11, graph=True,
+                                          poll_every=6)
+        assert np.array_equal(host(xg), host(xd))
+        assert [i["iters"] for i in ig] == [i["iters"] for i in idd]
+        assert np.array_equal(rg, rd) and np.array_equal(sg, sd)
