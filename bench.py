@@ -1,0 +1,195 @@
+"""Benchmark: lambda-sweep PCG solves per second on one MI355X.
+
+Workload (the 512 x 512 deblurring configuration): 15 x 15 Gaussian PSF
+(sigma = 3) with reflective boundary, Neumann gradient, seeded
+piecewise-constant phantom with 1% noise, three outer weightings
+(D = I, then seeded edge weights in [0.01, 1]) and 20 lambdas log-spaced in
+[1e-5, 1]; a six-level V-cycle preconditioner.  One step = for every outer
+weighting: install the weights (Galerkin hierarchy) and solve the whole
+lambda sweep to relative residual 1e-12, the tolerance at which every
+solution is within relative error 1e-6 of the FP64 oracle (checked by the
+GPU test suite at this size).  60 solves per step, FP64 throughout.
+
+Prints one JSON line.  `value` = solves / second of the timed steps with the
+inputs resident in HBM.  `roofline` reports the most frequent kernel (the
+finest-level Chebyshev smoothing step) from live HIP-event timing of every
+launch in a separate pass over the same step.  `cpu_baseline` times the CPU
+oracle on a bounded sample (see its `sample` field).
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+TOL = 1e-12
+NU_FINE, RATIO_FINE = 32, 400.0
+NU_COARSE, RATIO_COARSE = 2, 4.0
+HBM_PEAK_GBS = 8000.0
+
+
+def workload_config(P_):
+    return {
+        "workload": (f"deblur {P_.nv}x{P_.nh}, 15x15 Gaussian PSF sigma=3, "
+                     "reflective blur, Neumann gradient, 3 outer weightings x "
+                     f"{len(P_.lams)} lambdas in [1e-5, 1], {P_.levels}-level "
+                     f"V-cycle (Chebyshev nu={NU_FINE} fine / {NU_COARSE} "
+                     f"coarse), rel. residual {TOL:g} (rel. error <= 1e-6)"),
+        "n": P_.nv * P_.nh,
+        "lambdas": len(P_.lams),
+        "outer": len(P_.weights),
+        "solves_per_step": len(P_.lams) * len(P_.weights),
+    }
+
+
+def run_step(prob, b, D, lams, timer=False):
+    infos = []
+    for d in D:
+        prob.set_weights(d)
+        _, _, _, info = prob.solve_sweep(b, lams, TOL, maxit=400000,
+                                         poll_every=16)
+        infos.append(info)
+    return infos
+
+
+def cpu_baseline(P_, iters_per_slot, budget_s=20.0):
+    """Time the oracle's V-cycle-preconditioned CG on the same workload for a
+    bounded number of iterations and extrapolate with the per-lambda
+    iteration counts of the GPU run (the two agree to +-1 iteration)."""
+    import numpy as np
+
+    from oracle.pcg import DeblurOracle, pcg
+
+    O = DeblurOracle(P_.nv, P_.nh, P_.taps_v, P_.taps_h, P_.bc, P_.lbc,
+                     P_.weights[1], P_.levels)
+    lam = float(P_.lams[0])
+    nus = [NU_FINE] + [NU_COARSE] * (P_.levels - 1)
+    ratios = [RATIO_FINE] + [RATIO_COARSE] * (P_.levels - 1)
+    t_setup0 = time.perf_counter()
+    c0 = time.process_time()
+    V = O.vcycle(lam, nu=nus, ratio=ratios)
+    K = O.K(lam)
+    f = O.rhs(P_.b)
+    t_setup = time.perf_counter() - t_setup0
+    # one iteration to size the sample, then one bounded run
+    t1 = time.perf_counter()
+    pcg(K, f, V, tol=0.0, maxit=1)
+    one = time.perf_counter() - t1
+    total_its = max(2, int(budget_s / max(one, 1e-3)))
+    t0 = time.perf_counter()
+    pcg(K, f, V, tol=0.0, maxit=total_its)
+    wall = time.perf_counter() - t0
+    cpu = time.process_time() - c0
+    per_it = wall / total_its
+    total_slot_its = float(np.sum(iters_per_slot))
+    solves = len(iters_per_slot)
+    est = total_slot_its * per_it
+    return {
+        "value": solves / est,
+        "unit": "solves/s",
+        "cores": max(1, round(cpu / (wall + t_setup))),
+        "kind": "oracle",
+        "sample": (f"{total_its} MG-PCG iterations of the CPU oracle (numpy/"
+                   f"scipy FP64) at lambda={lam:g}, outer weighting 1, "
+                   f"{wall:.1f} s; time per iteration {per_it:.3f} s "
+                   f"extrapolated to the {int(total_slot_its)} iterations the "
+                   f"{solves} solves of one step take"),
+    }
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=1)
+    ap.add_argument("--warmup", type=int, default=0)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-roofline", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py runs on one GPU only (got --gpus {args.gpus}); the "
+              "lambda sweep is solved on a single MI355X", file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+
+    import workloads as W
+    from paper_2306_11067_amd import Problem
+
+    P_ = W.config2()
+    dev = torch.device("cuda:0")
+    b = torch.as_tensor(P_.b).to(dev)
+    D = [torch.as_tensor(w).to(dev) for w in P_.weights]
+    lams = np.asarray(P_.lams)
+    prob = Problem(P_.nv, P_.nh, P_.taps_v, P_.taps_h, P_.bc, P_.lbc,
+                   P_.levels, nu=NU_FINE, cheb_ratio=RATIO_FINE, weights=D[0],
+                   nu_coarse=NU_COARSE, cheb_ratio_coarse=RATIO_COARSE)
+    # load every kernel once (not a step)
+    prob.solve_sweep(b, lams, TOL, maxit=2, poll_every=2)
+    for _ in range(args.warmup):
+        run_step(prob, b, D, lams)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    infos = []
+    for _ in range(args.steps):
+        infos = run_step(prob, b, D, lams)
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+    solves = args.steps * len(lams) * len(D)
+    conv = all(i["flags"] & 1 for info in infos for i in info)
+    iters = [i["iters"] for info in infos for i in info]
+    print(f"timed {args.steps} step(s) in {elapsed:.2f} s, all converged: "
+          f"{conv}, max iterations {max(iters)}", file=sys.stderr, flush=True)
+
+    roof = None
+    if not args.no_roofline:
+        prob.kernel_timer(True)
+        run_step(prob, b, D, lams)
+        torch.cuda.synchronize()
+        launches, seconds, nbytes = prob.kernel_timer_read()
+        prob.kernel_timer(False)
+        avg_s = seconds / max(launches, 1)
+        achieved = (nbytes / max(launches, 1)) / avg_s / 1e9
+        roof = {"bound": "hbm", "achieved": round(achieved, 1),
+                "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
+                "kernel": "k_apply<PRO_PLAIN, EPI_CHEB> (finest level)",
+                "launches": launches,
+                "avg_launch_us": round(1e6 * avg_s, 3),
+                "bytes_per_launch": round(nbytes / max(launches, 1))}
+        print(f"roofline pass: {launches} launches, {1e6 * avg_s:.2f} us "
+              f"avg, {achieved:.1f} GB/s", file=sys.stderr, flush=True)
+
+    cpu = None
+    if not args.no_cpu_baseline:
+        cpu = cpu_baseline(P_, iters)
+
+    out = {
+        "metric": ("lambda-sweep PCG solves/sec at rel.err 1e-6 vs FP64 "
+                   "oracle; % HBM roofline"),
+        "value": solves / elapsed,
+        "unit": "solves/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": 1e3 * elapsed / args.steps,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic (seeded phantom, PSF, noise and edge weights)",
+        "config": workload_config(P_),
+        "roofline": roof,
+        "cpu_baseline": cpu,
+    }
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

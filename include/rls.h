@@ -107,10 +107,14 @@ typedef struct {
                                solved exactly (Algorithm 1), at most 1024
                                unknowns, every level at least 4 x 4          */
     int nu;                 /* Chebyshev smoothing steps before and after the
-                               coarse correction (V(nu,nu)), 1..8            */
-    double cheb_ratio;      /* smoothing interval [rho/ratio, rho], rho the
-                               Gershgorin bound of diag(K_k)^-1 K_k; > 1     */
+                               coarse correction on the finest level
+                               (V(nu,nu)), 1..64                            */
+    double cheb_ratio;      /* finest-level smoothing interval
+                               [rho/ratio, rho], rho the Gershgorin bound of
+                               diag(K_k)^-1 K_k; > 1                         */
     int precision;          /* RLS_PREC_FP64                                 */
+    int nu_coarse;          /* same on the coarser levels (0: = nu), 1..64  */
+    double cheb_ratio_coarse; /* same on the coarser levels (0: = cheb_ratio) */
 } rls_grid_desc;
 
 typedef struct {
@@ -211,6 +215,20 @@ rls_status rls_get_gram_band(const rls_problem* p, int level, int dir,
  * Chebyshev interval: rho (host) receives nlam values. */
 rls_status rls_gershgorin(rls_problem* p, int level, const double* lam,
                           int nlam, double* rho, void* stream);
+
+/* Live timing of the sweep's most frequent kernel: the finest-level level
+ * operator with the Chebyshev-step epilogue and a plain prologue (all but
+ * two of the 2 nu - 1 finest-level smoothing launches of a V-cycle).  While
+ * enabled, rls_solve_sweep launches kernels one by one instead of replaying
+ * graphs, and brackets every such launch with a pair of HIP events on the
+ * caller's stream.  rls_kernel_timer(p, 1) enables and resets, (p, 0)
+ * disables.  rls_kernel_timer_read returns the number of timed launches,
+ * their summed duration in seconds and their summed algorithmic bytes: per
+ * pixel, 40 bytes per active lambda (read x, f, d; write x, d) plus 24 bytes
+ * of shared stencil coefficients, every array counted once. */
+rls_status rls_kernel_timer(rls_problem* p, int enable);
+rls_status rls_kernel_timer_read(const rls_problem* p, long long* launches,
+                                 double* seconds, double* bytes);
 
 /* y = A x (forward blur) or x = A^T y for nvec vectors (device). */
 rls_status rls_apply_forward(rls_problem* p, const double* x, double* y,

@@ -168,11 +168,17 @@ def chebyshev(K, dinv, b, x, a: float, bnd: float, steps: int):
 
 
 class VCycle:
-    """z = M^{-1} r by one V(nu, nu) cycle (Algorithm 1, gamma = 1)."""
+    """z = M^{-1} r by one V(nu, nu) cycle (Algorithm 1, gamma = 1).
 
-    def __init__(self, H: Hierarchy, lam: float, nu: int = 2,
-                 ratio: float = 4.0):
-        self.H, self.lam, self.nu, self.ratio = H, lam, nu, ratio
+    nu and ratio may be given per level (sequences indexed by level, finest
+    first); a scalar applies to every level.
+    """
+
+    def __init__(self, H: Hierarchy, lam: float, nu=2, ratio=4.0):
+        self.H, self.lam = H, lam
+        L = H.levels
+        self.nu = list(nu) if hasattr(nu, "__len__") else [nu] * L
+        self.ratio = list(ratio) if hasattr(ratio, "__len__") else [ratio] * L
         self.dinv = [1.0 / H.diag(k, lam) for k in range(H.levels)]
         self.rho = [H.gershgorin(k, lam) for k in range(H.levels)]
         self.chol = sla.cho_factor(H.coarse_matrix(lam), lower=True)
@@ -182,11 +188,11 @@ class VCycle:
         if k == H.levels - 1:
             return sla.cho_solve(self.chol, b)
         K = lambda v: H.K(k, lam, v)
-        lo, hi = self.rho[k] / self.ratio, self.rho[k]
-        x = chebyshev(K, self.dinv[k], b, None, lo, hi, self.nu)
+        lo, hi = self.rho[k] / self.ratio[k], self.rho[k]
+        x = chebyshev(K, self.dinv[k], b, None, lo, hi, self.nu[k])
         res = b - K(x)
         e = self.cycle(H.P[k].T @ res, k + 1)
         x = x + H.P[k] @ e
-        return chebyshev(K, self.dinv[k], b, x, lo, hi, self.nu)
+        return chebyshev(K, self.dinv[k], b, x, lo, hi, self.nu[k])
 
     __call__ = cycle

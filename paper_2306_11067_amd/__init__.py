@@ -57,7 +57,8 @@ class Problem:
     """One regularized least-squares problem (A, L, grid) on the GPU."""
 
     def __init__(self, nv, nh, taps_v, taps_h, bc="reflective", lbc="neumann",
-                 levels=3, nu=2, cheb_ratio=4.0, weights=None):
+                 levels=3, nu=2, cheb_ratio=4.0, weights=None, nu_coarse=0,
+                 cheb_ratio_coarse=0.0):
         self._lib = L.load()
         self.nv, self.nh, self.levels = int(nv), int(nh), int(levels)
         self.n = self.nv * self.nh
@@ -70,7 +71,8 @@ class Problem:
         op.r_h = (len(th) - 1) // 2
         op.taps_v, op.taps_h = ptv, pth
         g = L.GridDesc(self.nv, self.nh, LBC[lbc], self.levels, int(nu),
-                       float(cheb_ratio), L.RLS_PREC_FP64)
+                       float(cheb_ratio), L.RLS_PREC_FP64, int(nu_coarse),
+                       float(cheb_ratio_coarse))
         h = C.c_void_p()
         d = None if weights is None else _dptr(weights, "weights", 2 * self.n)
         _check(self._lib.rls_setup(C.byref(h), C.byref(op), C.byref(g), d,
@@ -168,6 +170,15 @@ class Problem:
             self._h, level, plam, len(lam),
             rho.ctypes.data_as(C.POINTER(C.c_double)), _stream()))
         return rho
+
+    def kernel_timer(self, enable=True):
+        _check(self._lib.rls_kernel_timer(self._h, 1 if enable else 0))
+
+    def kernel_timer_read(self):
+        n, sec, byt = C.c_longlong(), C.c_double(), C.c_double()
+        _check(self._lib.rls_kernel_timer_read(self._h, C.byref(n),
+                                               C.byref(sec), C.byref(byt)))
+        return n.value, sec.value, byt.value
 
     def forward(self, x, nvec=1):
         import torch

@@ -33,7 +33,8 @@ EXPORTS = [
     "rls_setup", "rls_set_weights", "rls_solve_sweep", "rls_destroy",
     "rls_last_error", "rls_level_shape", "rls_apply_normal", "rls_vcycle",
     "rls_get_stencil", "rls_get_gram_band", "rls_gershgorin",
-    "rls_apply_forward", "rls_apply_adjoint",
+    "rls_apply_forward", "rls_apply_adjoint", "rls_kernel_timer",
+    "rls_kernel_timer_read",
 ]
 
 
@@ -48,7 +49,8 @@ class OpDesc(C.Structure):
 class GridDesc(C.Structure):
     _fields_ = [("nv", C.c_int), ("nh", C.c_int), ("lbc", C.c_int),
                 ("levels", C.c_int), ("nu", C.c_int),
-                ("cheb_ratio", C.c_double), ("precision", C.c_int)]
+                ("cheb_ratio", C.c_double), ("precision", C.c_int),
+                ("nu_coarse", C.c_int), ("cheb_ratio_coarse", C.c_double)]
 
 
 class SweepOpts(C.Structure):
@@ -86,6 +88,10 @@ def _declare(lib):
     lib.rls_gershgorin.argtypes = [_P, C.c_int, _D, C.c_int, _D, _P]
     lib.rls_apply_forward.argtypes = [_P, _P, _P, C.c_int, _P]
     lib.rls_apply_adjoint.argtypes = [_P, _P, _P, C.c_int, _P]
+    lib.rls_kernel_timer.argtypes = [_P, C.c_int]
+    lib.rls_kernel_timer_read.argtypes = [_P, C.POINTER(C.c_longlong),
+                                          C.POINTER(C.c_double),
+                                          C.POINTER(C.c_double)]
     for name in EXPORTS:
         if name not in ("rls_destroy", "rls_last_error"):
             getattr(lib, name).restype = C.c_int

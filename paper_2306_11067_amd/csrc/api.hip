@@ -137,8 +137,10 @@ struct Work {
 
 struct rls_problem {
     int device = 0;
-    int nv = 0, nh = 0, levels = 0, nu = 2, bc = 0, lbc = 0;
-    double ratio = 4.0;
+    int nv = 0, nh = 0, levels = 0, bc = 0, lbc = 0;
+    std::vector<int> nu;         // Chebyshev steps per level
+    std::vector<double> ratio;   // Chebyshev interval ratio per level
+    int nu_max = 2;
     int periodic = 0;            // multigrid / gradient periodicity
     int r_v = 0, r_h = 0;
     std::vector<double> taps_v, taps_h;
@@ -148,9 +150,16 @@ struct rls_problem {
     int unit_weights = 1;
     Work w;
     hipStream_t cstream = nullptr;   // capture stream for iteration graphs
+    // live timing of the finest-level Chebyshev-step kernel
+    bool timer_on = false;
+    std::vector<std::pair<hipEvent_t, hipEvent_t>> ev_pool, ev_pending;
+    long long timer_launches = 0, timer_counted = 0;
+    double timer_seconds = 0.0, timer_bytes = 0.0;
     int kt = 0;                      // first level handled by the tail kernel
     int64_t n() const { return (int64_t)nv * nh; }
     ~rls_problem() {
+        for (auto& e : ev_pool) { hipEventDestroy(e.first); hipEventDestroy(e.second); }
+        for (auto& e : ev_pending) { hipEventDestroy(e.first); hipEventDestroy(e.second); }
         if (cstream) hipStreamDestroy(cstream);
     }
 };
@@ -170,6 +179,36 @@ rls_status check_launch(const char* where) {
     return RLS_OK;
 }
 
+// Timed launch of the finest-level Chebyshev-step kernel.
+void timed_apply(rls_problem* P, int pro, int epi, const ApplyArgs& a,
+                 hipStream_t s) {
+    std::pair<hipEvent_t, hipEvent_t> ev;
+    if (P->ev_pool.empty()) {
+        hipEventCreate(&ev.first);
+        hipEventCreate(&ev.second);
+    } else {
+        ev = P->ev_pool.back();
+        P->ev_pool.pop_back();
+    }
+    hipEventRecord(ev.first, s);
+    launch_apply(pro, epi, a, s);
+    hipEventRecord(ev.second, s);
+    P->ev_pending.push_back(ev);
+}
+
+// Fold completed event pairs into the timer totals (stream synchronized).
+void drain_timer(rls_problem* P) {
+    for (auto& ev : P->ev_pending) {
+        float ms = 0.f;
+        if (hipEventElapsedTime(&ms, ev.first, ev.second) == hipSuccess) {
+            P->timer_seconds += 1e-3 * ms;
+            P->timer_launches += 1;
+        }
+        P->ev_pool.push_back(ev);
+    }
+    P->ev_pending.clear();
+}
+
 rls_status ensure_work(rls_problem* P, int nslot) {
     Work& w = P->w;
     if (w.cap >= nslot) return RLS_OK;
@@ -184,7 +223,7 @@ rls_status ensure_work(rls_problem* P, int nslot) {
     RLS_TRY(dalloc(w.beta, sizeof(double) * cap));
     RLS_TRY(dalloc(w.part, sizeof(double) * (size_t)cap * max_part_slots(P)));
     RLS_TRY(dalloc(w.rho, sizeof(double) * (size_t)cap * L));
-    RLS_TRY(dalloc(w.cheb, sizeof(double) * (size_t)cap * L * 2 * P->nu));
+    RLS_TRY(dalloc(w.cheb, sizeof(double) * (size_t)cap * L * 2 * P->nu_max));
     const int64_t nc = P->lev.back().n();
     RLS_TRY(dalloc(w.kc, sizeof(double) * (size_t)cap * nc * nc));
     RLS_TRY(dalloc(w.winv, sizeof(double) * (size_t)cap * 2 * nc * nc));
@@ -375,11 +414,11 @@ rls_status upload_lam(rls_problem* P, const double* lam, int nlam,
 rls_status prepare_sweep(rls_problem* P, int nslot, hipStream_t s) {
     Work& w = P->w;
     const int L = P->levels;
-    const int cs = 2 * P->nu;
+    const int cs = 2 * P->nu_max;
     for (int k = 0; k + 1 < L; ++k) {
         double* rho = w.rho.as<double>() + (size_t)k * w.cap;
         launch_gershgorin(P->lev[k].geom(), w.lam2.as<double>(), nslot, rho, s);
-        launch_cheb_coeffs(rho, nslot, P->ratio, P->nu,
+        launch_cheb_coeffs(rho, nslot, P->ratio[k], P->nu[k], cs,
                            w.cheb.as<double>() + (size_t)k * w.cap * cs, s);
     }
     const Level& C = P->lev[L - 1];
@@ -421,8 +460,8 @@ void vcycle(rls_problem* P, int k, int nslot, const int* slots,
             hipStream_t s) {
     Work& w = P->w;
     const int L = P->levels;
-    const int cs = 2 * P->nu;
-    const int nu = P->nu;
+    const int cs = 2 * P->nu_max;
+    const int nu = P->nu[k];
     const bool top = k == 0;
     if (k >= P->kt) {
         TailArgs t;
@@ -435,8 +474,8 @@ void vcycle(rls_problem* P, int k, int nslot, const int* slots,
             t.lev[i].gh = g.gh;
             t.lev[i].S = g.S;
             t.lev[i].cheb = w.cheb.as<double>() + (size_t)(k + i) * w.cap * cs;
+            t.lev[i].nu = P->nu[k + i];
         }
-        t.nu = nu;
         t.cheb_stride = cs;
         t.periodic = P->periodic;
         t.lam2 = w.lam2.as<double>();
@@ -522,7 +561,8 @@ void vcycle(rls_problem* P, int k, int nslot, const int* slots,
         c.in = bufs[cur];
         c.out = bufs[1 - cur];
         c.cheb = cheb + 2 * st;
-        launch_apply(PRO_PLAIN, EPI_CHEB, c, s);
+        if (top && P->timer_on) timed_apply(P, PRO_PLAIN, EPI_CHEB, c, s);
+        else launch_apply(PRO_PLAIN, EPI_CHEB, c, s);
         cur = 1 - cur;
     }
     {
@@ -543,7 +583,8 @@ void vcycle(rls_problem* P, int k, int nslot, const int* slots,
             c.part = ctl.dot_part;
             c.part_stride = ctl.dot_stride;
         }
-        launch_apply(st == 0 ? PRO_PROLONG : PRO_PLAIN, EPI_CHEB, c, s);
+        if (top && st > 0 && P->timer_on) timed_apply(P, PRO_PLAIN, EPI_CHEB, c, s);
+        else launch_apply(st == 0 ? PRO_PROLONG : PRO_PLAIN, EPI_CHEB, c, s);
         cur = 1 - cur;
     }
 }
@@ -551,9 +592,14 @@ void vcycle(rls_problem* P, int k, int nslot, const int* slots,
 rls_status validate_grid(const rls_grid_desc* g) {
     if (g->nv < 4 || g->nh < 4) return fail(RLS_E_ARG, "grid must be >= 4 x 4");
     if (g->levels < 1 || g->levels > 16) return fail(RLS_E_ARG, "levels in 1..16");
-    if (g->nu < 1 || g->nu > 8) return fail(RLS_E_ARG, "nu in 1..8");
+    if (g->nu < 1 || g->nu > 64) return fail(RLS_E_ARG, "nu in 1..64");
+    if (g->nu_coarse < 0 || g->nu_coarse > 64)
+        return fail(RLS_E_ARG, "nu_coarse in 0..64");
     if (!(g->cheb_ratio > 1.0) || !std::isfinite(g->cheb_ratio))
         return fail(RLS_E_ARG, "cheb_ratio must be > 1");
+    if (g->cheb_ratio_coarse != 0.0 &&
+        (!(g->cheb_ratio_coarse > 1.0) || !std::isfinite(g->cheb_ratio_coarse)))
+        return fail(RLS_E_ARG, "cheb_ratio_coarse must be 0 or > 1");
     if (g->lbc != RLS_L_NEUMANN && g->lbc != RLS_L_PERIODIC)
         return fail(RLS_E_ARG, "unknown gradient boundary");
     for (int k = 0; k < g->levels; ++k) {
@@ -607,8 +653,13 @@ rls_status rls_setup(rls_problem** out, const rls_op_desc* A,
     P->nv = g->nv;
     P->nh = g->nh;
     P->levels = g->levels;
-    P->nu = g->nu;
-    P->ratio = g->cheb_ratio;
+    for (int k = 0; k < g->levels; ++k) {
+        const bool fine = k == 0;
+        P->nu.push_back(fine || g->nu_coarse == 0 ? g->nu : g->nu_coarse);
+        P->ratio.push_back(fine || g->cheb_ratio_coarse == 0.0
+                               ? g->cheb_ratio : g->cheb_ratio_coarse);
+    }
+    P->nu_max = *std::max_element(P->nu.begin(), P->nu.end());
     P->bc = A->bc;
     P->lbc = g->lbc;
     P->periodic = g->lbc == RLS_L_PERIODIC;
@@ -729,6 +780,23 @@ rls_status rls_vcycle(rls_problem* p, const double* lam, int nlam,
     vcycle(p, 0, nlam, nullptr, nullptr, r, z, CycleCtl(), s);
     RLS_TRY(check_launch("rls_vcycle"));
     RLS_HIP(hipStreamSynchronize(s));
+    return RLS_OK;
+}
+
+rls_status rls_kernel_timer(rls_problem* p, int enable) {
+    if (!p) return fail(RLS_E_STATE, "null handle");
+    p->timer_on = enable != 0;
+    p->timer_launches = p->timer_counted = 0;
+    p->timer_seconds = p->timer_bytes = 0.0;
+    return RLS_OK;
+}
+
+rls_status rls_kernel_timer_read(const rls_problem* p, long long* launches,
+                                 double* seconds, double* bytes) {
+    if (!p) return fail(RLS_E_STATE, "null handle");
+    if (launches) *launches = p->timer_launches;
+    if (seconds) *seconds = p->timer_seconds;
+    if (bytes) *bytes = p->timer_bytes;
     return RLS_OK;
 }
 
@@ -888,13 +956,14 @@ rls_status rls_solve_sweep(rls_problem* p, const double* b, const double* lam,
         RLS_HIP(hipMemcpyAsync(hact, active, sizeof(int) * ns,
                                hipMemcpyDeviceToHost, s));
         RLS_HIP(hipStreamSynchronize(s));
+        if (p->timer_on) drain_timer(p);
         int nact = 0;
         for (int i = 0; i < ns; ++i)
             if (hact[i]) hsl[nact++] = i;
         if (nact == 0) break;
         RLS_HIP(hipMemcpyAsync(w.slots.p, hsl, sizeof(int) * nact,
                                hipMemcpyHostToDevice, s));
-        if (!o.graph) {
+        if (!o.graph || p->timer_on) {
             for (int k = 0; k < chunk; ++k) iteration(nact, k & 1, s);
             status = check_launch("pcg iteration");
             if (status != RLS_OK) break;
@@ -958,6 +1027,17 @@ rls_status rls_solve_sweep(rls_problem* p, const double* b, const double* lam,
     RLS_HIP(hipMemcpyAsync(hst.data(), st, sizeof(SlotState) * ns,
                            hipMemcpyDeviceToHost, s));
     RLS_HIP(hipStreamSynchronize(s));
+    if (p->timer_on) {
+        drain_timer(p);
+        // every V-cycle of a slot takes part in 2 nu - 3 timed launches
+        const int nu0 = p->nu[0];
+        const int per_cycle = (p->levels > 1 && p->kt > 0 && nu0 >= 2) ? 2 * nu0 - 3 : 0;
+        double slot_launches = 0.0;
+        for (int i = 0; i < ns; ++i) slot_launches += (double)hst[i].ncycle * per_cycle;
+        p->timer_bytes += (double)n * (40.0 * slot_launches) +
+                          (double)n * 24.0 * (double)(p->timer_launches - p->timer_counted);
+        p->timer_counted = p->timer_launches;
+    }
     for (int i = 0; i < ns; ++i) {
         if (resnorm) resnorm[i] = std::sqrt(h3[ns + i]);
         if (seminorm) seminorm[i] = std::sqrt(h3[2 * ns + i]);

@@ -14,6 +14,9 @@
 // A_k^T A_k = G_h (x) G_v, and M_k^T M_k is the Galerkin stencil of
 // L^T D^2 L.  The prologues and epilogues fuse the surrounding steps of the
 // V-cycle (Algorithm 1) and of PCG into the same pass over the tile.
+#include <cstdio>
+#include <cstdlib>
+
 #include "common.h"
 #include "pcg_ctl.h"
 
@@ -54,30 +57,74 @@ __device__ __forceinline__ double prolong_at(const double* __restrict__ e,
     return s;
 }
 
+// Register window of the vertical pass for uniform bands: each thread
+// produces VWIN consecutive rows of one column, consuming the taps VCH at
+// a time (taps zero-padded to a multiple of VCH).
+constexpr int VWIN = 8;
+constexpr int VCH = 8;
+
 struct TileShape {
-    int lo, hv, hh, RY, SY, CX, SO, RO, CO, SR, WV, WH, NCV, NCH;
+    int lo, hv, hh, RY, SY, CX, SO, RO, CO, SR, WV, WVP, WH, NCV, NCH;
     __host__ __device__ TileShape(const LevelGeom& g, int ext) {
         lo = ext;
         hv = (g.gv.bw > 1 ? g.gv.bw : 1) + lo;
         hh = (g.gh.bw > 1 ? g.gh.bw : 1) + lo;
         RY = TILE_Y + 2 * hv;
-        SY = RY | 1;
+        SY = (RY + VWIN + VCH) | 1;   // slack rows read by the last window
         CX = TILE_X + 2 * hh;
-        RO = TILE_Y + lo;          // output rows (incl. low extension)
+        RO = TILE_Y + lo;             // output rows (incl. low extension)
         CO = TILE_X + lo;
         SO = RO | 1;
         SR = RO | 1;
         WV = 2 * g.gv.bw + 1;
+        WVP = (WV + VCH - 1) / VCH * VCH;
         WH = 2 * g.gh.bw + 1;
-        NCV = g.gv.uniform ? 1 : RO;   // staged coefficient rows
+        NCV = g.gv.uniform ? 1 : RO;  // staged coefficient rows
         NCH = g.gh.uniform ? 1 : CO;
     }
     __host__ __device__ size_t lds_doubles(int restrict_) const {
         return (size_t)CX * SY + (size_t)CX * SO +
-               (restrict_ ? (size_t)CO * SR : 0) + (size_t)NCV * WV +
+               (restrict_ ? (size_t)CO * SR : 0) + (size_t)NCV * WVP +
                (size_t)NCH * WH;
     }
 };
+
+// Vertical pass of a uniform band with the chunked register window.
+__device__ __forceinline__ void vert_window(const double* __restrict__ vin,
+                                            double* __restrict__ vt,
+                                            const double* __restrict__ taps,
+                                            const TileShape& T, int bw, int i0,
+                                            int nv, int per) {
+    const int nseg = (T.RO + VWIN - 1) / VWIN;
+    for (int e = threadIdx.x; e < nseg * T.CX; e += APPLY_THREADS) {
+        const int sg = e / T.CX, jj = e - sg * T.CX;   // lanes along columns
+        const int r0 = sg * VWIN;
+        const double* col = vin + jj * T.SY + r0 - T.lo + T.hv - bw;
+        double acc[VWIN];
+#pragma unroll
+        for (int o = 0; o < VWIN; ++o) acc[o] = 0.0;
+        for (int c0 = 0; c0 < T.WVP; c0 += VCH) {
+            double win[VWIN + VCH - 1];
+            double tp[VCH];
+#pragma unroll
+            for (int m = 0; m < VWIN + VCH - 1; ++m) win[m] = col[c0 + m];
+#pragma unroll
+            for (int k = 0; k < VCH; ++k) tp[k] = taps[c0 + k];
+#pragma unroll
+            for (int k = 0; k < VCH; ++k)
+#pragma unroll
+                for (int o = 0; o < VWIN; ++o) acc[o] += tp[k] * win[o + k];
+        }
+#pragma unroll
+        for (int o = 0; o < VWIN; ++o) {
+            const int r = r0 + o;
+            if (r >= T.RO) break;
+            const int gi = i0 + r - T.lo;
+            const bool ok = gi < nv && (gi >= 0 || per);
+            vt[jj * T.SO + r] = ok ? acc[o] : 0.0;
+        }
+    }
+}
 
 template <int PRO, int EPI>
 __global__ void __launch_bounds__(APPLY_THREADS) k_apply(ApplyArgs a) {
@@ -89,21 +136,28 @@ __global__ void __launch_bounds__(APPLY_THREADS) k_apply(ApplyArgs a) {
     const LevelGeom& g = a.g;
     const int nv = g.nv, nh = g.nh;
     const int64_t n = (int64_t)nv * nh;
-    const int i0 = blockIdx.x * TILE_Y, j0 = blockIdx.y * TILE_X;
-    const int bwv = g.gv.bw, bwh = g.gh.bw;
+    // XCD-aware tile order: workgroups are dealt round-robin over the 8
+    // XCDs, so give each XCD a contiguous run of tiles (shared halos stay
+    // in that XCD's L2) when the tile count allows it.
+    const int ntx = gridDim.x, nty = gridDim.y, ntile = ntx * nty;
+    int tile = blockIdx.x + ntx * blockIdx.y;
+    if ((ntile & 7) == 0) tile = (tile & 7) * (ntile >> 3) + (tile >> 3);
+    const int tx = tile % ntx, ty = tile / ntx;
+    const int i0 = tx * TILE_Y, j0 = ty * TILE_X;
     const TileShape T(g, EXT);
+    const int bwv = g.gv.bw, bwh = g.gh.bw;
     double* vin = lds;
     double* vt = vin + T.CX * T.SY;
     double* rs = vt + T.CX * T.SO;
     double* cv = rs + (EXT ? T.CO * T.SR : 0);
-    double* ch = cv + T.NCV * T.WV;
+    double* ch = cv + T.NCV * T.WVP;
     const size_t so = (size_t)slot * n;
     const double* src = a.in ? a.in + so : nullptr;
     const double l2 = a.lam2[slot];
     const int per = g.S.periodic;
 
-    // PCG scalars folded into this kernel; tile (0, 0) of a slot leads
-    const bool lead = blockIdx.x == 0 && blockIdx.y == 0;
+    // PCG scalars folded into this kernel; tile 0 of a slot leads
+    const bool lead = tile == 0;
     double beta = 0.0, cj = 0.0;
     if (PRO == PRO_PUPDATE) {
         if (!pcg_beta<APPLY_THREADS>(a.st, a.active_w, slot, a.part_rz, a.nrz,
@@ -119,15 +173,17 @@ __global__ void __launch_bounds__(APPLY_THREADS) k_apply(ApplyArgs a) {
         cj = a.cheb_first[(size_t)slot * a.cheb_stride + 1];
 
     // 1. stage band coefficients, load v with prologue
-    for (int e = threadIdx.x; e < T.NCV * T.WV; e += APPLY_THREADS) {
-        const int r = e / T.WV, k = e - r * T.WV;
+    for (int e = threadIdx.x; e < T.NCV * T.WVP; e += APPLY_THREADS) {
+        const int r = e / T.WVP, k = e - r * T.WVP;
         double c = 0.0;
-        if (g.gv.uniform) {
-            c = g.gv.taps[k];
-        } else {
-            int gi = i0 + r - T.lo;
-            if (gi < 0 && per) gi += nv;
-            if (gi >= 0 && gi < nv) c = g.gv.table[(size_t)gi * T.WV + k];
+        if (k < T.WV) {                           // zero padding to WVP
+            if (g.gv.uniform) {
+                c = g.gv.taps[k];
+            } else {
+                int gi = i0 + r - T.lo;
+                if (gi < 0 && per) gi += nv;
+                if (gi >= 0 && gi < nv) c = g.gv.table[(size_t)gi * T.WV + k];
+            }
         }
         cv[e] = c;
     }
@@ -176,13 +232,16 @@ __global__ void __launch_bounds__(APPLY_THREADS) k_apply(ApplyArgs a) {
     __syncthreads();
 
     // 2. vertical pass over output rows [-lo, TILE_Y) of every loaded column
+    if (g.gv.uniform) {
+        vert_window(vin, vt, cv, T, bwv, i0, nv, per);
+    } else
     for (int e = threadIdx.x; e < T.RO * T.CX; e += APPLY_THREADS) {
         const int jj = e / T.RO, r = e - jj * T.RO;        // r = row + lo
         const int gi = i0 + r - T.lo;
         double s = 0.0;
         if (gi < nv && (gi >= 0 || per)) {
             const double* col = vin + jj * T.SY + r - T.lo + T.hv - bwv;
-            const double* cf = cv + (g.gv.uniform ? 0 : r) * T.WV;
+            const double* cf = cv + r * T.WVP;
 #pragma unroll 4
             for (int k = 0; k < T.WV; ++k) s += cf[k] * col[k];
         }
@@ -283,48 +342,53 @@ __global__ void __launch_bounds__(APPLY_THREADS) k_apply(ApplyArgs a) {
     if (EPI == EPI_DOT || (EPI == EPI_CHEB && a.dot)) {
         const double s = block_sum<APPLY_THREADS>(dot, red);
         if (threadIdx.x == 0)
-            a.part[(size_t)slot * a.part_stride + blockIdx.x +
-                   (size_t)gridDim.x * blockIdx.y] = s;
+            a.part[(size_t)slot * a.part_stride + tile] = s;
     }
 }
 
 template <int PRO, int EPI>
-static void configure_t() {
+static void configure_one() {
     // dynamic LDS may use what the kernel's static LDS leaves of 160 KiB
     hipFuncAttributes attr;
     size_t stat = 0;
     if (hipFuncGetAttributes(&attr, (const void*)k_apply<PRO, EPI>) == hipSuccess)
         stat = attr.sharedSizeBytes;
-    hipFuncSetAttribute((const void*)k_apply<PRO, EPI>,
-                        hipFuncAttributeMaxDynamicSharedMemorySize,
-                        (int)(160 * 1024 - stat));
-}
-
-void configure_apply_kernels() {
-    static bool done = false;
-    if (done) return;
-    configure_t<PRO_PUPDATE, EPI_DOT>();
-    configure_t<PRO_JACOBI, EPI_CHEB>();
-    configure_t<PRO_JACOBI, EPI_RESTRICT>();
-    configure_t<PRO_PROLONG, EPI_CHEB>();
-    configure_t<PRO_PROLONG_JAC, EPI_CHEB>();
-    configure_t<PRO_PLAIN, EPI_STORE>();
-    configure_t<PRO_PLAIN, EPI_DOT>();
-    configure_t<PRO_PLAIN, EPI_RESID>();
-    configure_t<PRO_PLAIN, EPI_RESTRICT>();
-    configure_t<PRO_PLAIN, EPI_CHEB>();
-    hipGetLastError();
-    done = true;
+    (void)hipFuncSetAttribute((const void*)k_apply<PRO, EPI>,
+                              hipFuncAttributeMaxDynamicSharedMemorySize,
+                              (int)(160 * 1024 - stat));
 }
 
 template <int PRO, int EPI>
-static void launch_t(const ApplyArgs& a, hipStream_t s) {
+static void launch_one(const ApplyArgs& a, hipStream_t s) {
     const TileShape T(a.g, EPI == EPI_RESTRICT);
     dim3 grid((a.g.nv + TILE_Y - 1) / TILE_Y, (a.g.nh + TILE_X - 1) / TILE_X,
               a.nslot);
     hipLaunchKernelGGL((k_apply<PRO, EPI>), grid, dim3(APPLY_THREADS),
                        sizeof(double) * T.lds_doubles(EPI == EPI_RESTRICT), s,
                        a);
+}
+
+// Every (prologue, epilogue) pair in use.
+#define RLS_APPLY_VARIANTS(X)         \
+    X(PRO_PUPDATE, EPI_DOT)           \
+    X(PRO_JACOBI, EPI_CHEB)           \
+    X(PRO_JACOBI, EPI_RESTRICT)       \
+    X(PRO_PROLONG, EPI_CHEB)          \
+    X(PRO_PROLONG_JAC, EPI_CHEB)      \
+    X(PRO_PLAIN, EPI_STORE)           \
+    X(PRO_PLAIN, EPI_DOT)             \
+    X(PRO_PLAIN, EPI_RESID)           \
+    X(PRO_PLAIN, EPI_RESTRICT)        \
+    X(PRO_PLAIN, EPI_CHEB)
+
+void configure_apply_kernels() {
+    static bool done = false;
+    if (done) return;
+#define RLS_CFG(P, E) configure_one<P, E>();
+    RLS_APPLY_VARIANTS(RLS_CFG)
+#undef RLS_CFG
+    (void)hipGetLastError();
+    done = true;
 }
 
 int apply_tiles(const LevelGeom& g) {
@@ -337,23 +401,13 @@ size_t apply_lds_bytes(const LevelGeom& g, int epi) {
 }
 
 void launch_apply(int pro, int epi, const ApplyArgs& a, hipStream_t s) {
-    switch (pro) {
-        case PRO_PUPDATE: launch_t<PRO_PUPDATE, EPI_DOT>(a, s); return;
-        case PRO_JACOBI:
-            if (epi == EPI_RESTRICT) launch_t<PRO_JACOBI, EPI_RESTRICT>(a, s);
-            else launch_t<PRO_JACOBI, EPI_CHEB>(a, s);
-            return;
-        case PRO_PROLONG: launch_t<PRO_PROLONG, EPI_CHEB>(a, s); return;
-        case PRO_PROLONG_JAC: launch_t<PRO_PROLONG_JAC, EPI_CHEB>(a, s); return;
-        default: break;
-    }
-    switch (epi) {
-        case EPI_STORE: launch_t<PRO_PLAIN, EPI_STORE>(a, s); break;
-        case EPI_DOT: launch_t<PRO_PLAIN, EPI_DOT>(a, s); break;
-        case EPI_RESID: launch_t<PRO_PLAIN, EPI_RESID>(a, s); break;
-        case EPI_RESTRICT: launch_t<PRO_PLAIN, EPI_RESTRICT>(a, s); break;
-        default: launch_t<PRO_PLAIN, EPI_CHEB>(a, s); break;
-    }
+#define RLS_LAUNCH(P, E) \
+    if (pro == P && epi == E) { launch_one<P, E>(a, s); return; }
+    RLS_APPLY_VARIANTS(RLS_LAUNCH)
+#undef RLS_LAUNCH
+    std::fprintf(stderr, "rls: no level-operator kernel for prologue %d, "
+                         "epilogue %d\n", pro, epi);
+    std::abort();
 }
 
 }  // namespace rls

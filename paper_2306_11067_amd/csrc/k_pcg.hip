@@ -175,6 +175,7 @@ k_pcg_init(SlotState* __restrict__ st, const double* __restrict__ fparts,
         s.gam[0] = s.gam[1] = 0.0;
         s.alpha = 0.0;
         s.it = 0;
+        s.ncycle = 1;
         s.maxit = maxit;
         s.flags = 0;
         s.active = 1;

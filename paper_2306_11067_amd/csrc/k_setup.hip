@@ -263,13 +263,14 @@ k_gershgorin(LevelGeom g, const double* __restrict__ lam2,
 // (0, 1/theta); step s >= 1: rho_s = 1/(2 sigma - rho_{s-1}),
 // (c1, c2) = (rho_s rho_{s-1}, 2 rho_s / delta).
 __global__ void k_cheb_coeffs(const double* __restrict__ rho, int nslot,
-                              double ratio, int nu, double* __restrict__ cheb) {
+                              double ratio, int nu, int stride,
+                              double* __restrict__ cheb) {
     const int slot = blockIdx.x * blockDim.x + threadIdx.x;
     if (slot >= nslot) return;
     const double b = rho[slot], a = b / ratio;
     const double theta = 0.5 * (b + a), delta = 0.5 * (b - a);
     const double sigma = theta / delta;
-    double* c = cheb + (size_t)slot * 2 * nu;
+    double* c = cheb + (size_t)slot * stride;
     c[0] = 0.0;
     c[1] = 1.0 / theta;
     double rold = 1.0 / sigma;
@@ -435,9 +436,9 @@ void launch_gershgorin(const LevelGeom& g, const double* lam2, int nslot,
                        rho);
 }
 void launch_cheb_coeffs(const double* rho, int nslot, double ratio, int nu,
-                        double* cheb, hipStream_t s) {
+                        int stride, double* cheb, hipStream_t s) {
     hipLaunchKernelGGL(k_cheb_coeffs, dim3(nblk(nslot, 64)), dim3(64), 0, s,
-                       rho, nslot, ratio, nu, cheb);
+                       rho, nslot, ratio, nu, stride, cheb);
 }
 void launch_coarse_assemble(const LevelGeom& g, const double* lam2, int nslot,
                             double* Kc, hipStream_t s) {

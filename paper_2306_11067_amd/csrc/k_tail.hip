@@ -163,7 +163,7 @@ __global__ void __launch_bounds__(TAIL_THREADS) k_tail(TailArgs a) {
     for (int k = 0; k + 1 < nl; ++k) {
         const TailLevel& L = a.lev[k];
         const double* cheb = L.cheb + (size_t)slot * a.cheb_stride;
-        tail_smooth(L, l2, per, a.nu, cheb, true, X[k], F[k], sc);
+        tail_smooth(L, l2, per, L.nu, cheb, true, X[k], F[k], sc);
         const double* fk = F[k];
         double* res = sc.res;
         tail_apply(L, l2, per, X[k], sc.t,
@@ -248,7 +248,7 @@ __global__ void __launch_bounds__(TAIL_THREADS) k_tail(TailArgs a) {
         }
         __syncthreads();
         const double* cheb = L.cheb + (size_t)slot * a.cheb_stride;
-        tail_smooth(L, l2, per, a.nu, cheb, false, X[k], F[k], sc);
+        tail_smooth(L, l2, per, L.nu, cheb, false, X[k], F[k], sc);
     }
 
     // store z (and r . z partials when the tail is the whole cycle)

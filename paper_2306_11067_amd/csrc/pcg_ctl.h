@@ -97,6 +97,7 @@ __device__ __forceinline__ bool pcg_gate(SlotState* st, int* active, int slot,
         if (lead) stop_slot(st, active, slot, flag);
         return false;
     }
+    if (lead) st[slot].ncycle += 1;
     return true;
 }
 

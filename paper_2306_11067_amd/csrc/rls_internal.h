@@ -80,6 +80,7 @@ struct SlotState {
     double target;  // residual norm target
     double fnorm;   // ||A^T b||
     int it;         // completed iterations
+    int ncycle;     // V-cycles run (the initial one included)
     int active;
     int flags;
     int maxit;
@@ -141,7 +142,7 @@ void launch_stencil_rowabs(const double* planes, int nv, int nh, int periodic,
 void launch_gershgorin(const LevelGeom& g, const double* lam2, int nslot,
                        double* rho, hipStream_t s);
 void launch_cheb_coeffs(const double* rho, int nslot, double ratio, int nu,
-                        double* cheb, hipStream_t s);
+                        int stride, double* cheb, hipStream_t s);
 void launch_coarse_assemble(const LevelGeom& g, const double* lam2, int nslot,
                             double* Kc, hipStream_t s);
 void launch_cholesky_inverse(double* Kc, int n, int nslot, double* work,
@@ -202,12 +203,13 @@ struct TailLevel {
     BandDev gv, gh;                  // band tables are always present
     StencilDev S;
     const double* cheb = nullptr;    // per slot Chebyshev (c1, c2) pairs
+    int nu = 2;                      // smoothing steps on this level
 };
 
 struct TailArgs {
     int nlev = 0;                    // tail levels, the last is the coarsest
     TailLevel lev[TAIL_MAX_LEVELS];
-    int nu = 2, cheb_stride = 0, periodic = 0;
+    int cheb_stride = 0, periodic = 0;
     const double* lam2 = nullptr;
     const int* slots = nullptr;
     const int* active = nullptr;

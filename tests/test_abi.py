@@ -53,7 +53,7 @@ def test_grid_validation_without_gpu(field, value):
     op.bc = L.RLS_BC_REFLECTIVE
     op.r_v = op.r_h = 1
     op.taps_v = op.taps_h = C.cast(taps, C.POINTER(C.c_double))
-    g = L.GridDesc(64, 64, L.RLS_L_NEUMANN, 3, 2, 4.0, L.RLS_PREC_FP64)
+    g = L.GridDesc(64, 64, L.RLS_L_NEUMANN, 3, 2, 4.0, L.RLS_PREC_FP64, 0, 0.0)
     setattr(g, field, value)
     h = C.c_void_p()
     st = lib.rls_setup(C.byref(h), C.byref(op), C.byref(g), None, None)
@@ -69,7 +69,7 @@ def test_coarsest_size_limit_without_gpu():
     op.bc = L.RLS_BC_REFLECTIVE
     op.r_v = op.r_h = 1
     op.taps_v = op.taps_h = C.cast(taps, C.POINTER(C.c_double))
-    g = L.GridDesc(128, 128, L.RLS_L_NEUMANN, 2, 2, 4.0, L.RLS_PREC_FP64)
+    g = L.GridDesc(128, 128, L.RLS_L_NEUMANN, 2, 2, 4.0, L.RLS_PREC_FP64, 0, 0.0)
     h = C.c_void_p()
     assert lib.rls_setup(C.byref(h), C.byref(op), C.byref(g), None,
                          None) == L.RLS_E_ARG
@@ -84,7 +84,7 @@ def test_unsupported_boundary_pair_without_gpu():
     op.bc = L.RLS_BC_REFLECTIVE
     op.r_v = op.r_h = 1
     op.taps_v = op.taps_h = C.cast(taps, C.POINTER(C.c_double))
-    g = L.GridDesc(64, 64, L.RLS_L_PERIODIC, 3, 2, 4.0, L.RLS_PREC_FP64)
+    g = L.GridDesc(64, 64, L.RLS_L_PERIODIC, 3, 2, 4.0, L.RLS_PREC_FP64, 0, 0.0)
     h = C.c_void_p()
     assert lib.rls_setup(C.byref(h), C.byref(op), C.byref(g), None,
                          None) == L.RLS_E_UNSUPPORTED

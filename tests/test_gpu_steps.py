@@ -135,3 +135,26 @@ def test_unit_weights_stencil_is_laplacian():
     L = ops.gradient(nv, nh, "neumann")
     want = planes_from_sparse((L.T @ L).tocsr(), nv, nh, False)
     np.testing.assert_allclose(P.stencil(0), want, atol=0)
+
+
+@pytest.mark.parametrize("name", ["periodic64", "reflective96x72"])
+def test_vcycle_per_level_smoothing_matches_oracle(name):
+    # Heavier smoothing on the finest level than on the coarse ones.
+    from paper_2306_11067_amd import Problem
+    nv, nh, r, sg, bc, lbc, levels = CASES[name]
+    rng = np.random.default_rng(7)
+    tv = W.gaussian_taps(r, sg)
+    d = rng.uniform(0.01, 1.0, 2 * nv * nh)
+    O = DeblurOracle(nv, nh, tv, tv, bc, lbc, d, levels)
+    P = Problem(nv, nh, tv, tv, bc, lbc, levels, nu=7, cheb_ratio=60.0,
+                weights=dev(d), nu_coarse=3, cheb_ratio_coarse=5.0)
+    n = nv * nh
+    lams = np.array([1e-4, 0.3])
+    rr = rng.standard_normal(len(lams) * n)
+    got = host(P.vcycle(lams, dev(rr))).reshape(len(lams), n)
+    nus = [7] + [3] * (levels - 1)
+    ratios = [60.0] + [5.0] * (levels - 1)
+    for s, lam in enumerate(lams):
+        want = O.vcycle(lam, nu=nus, ratio=ratios)(rr[s * n:(s + 1) * n])
+        err = np.abs(got[s] - want).max() / np.abs(want).max()
+        assert err < 1e-10, (lam, err)
