@@ -12,8 +12,8 @@ GPU test suite at this size).  60 solves per step, FP64 throughout.
 
 Prints one JSON line.  `value` = solves / second of the timed steps with the
 inputs resident in HBM.  `roofline` reports the most frequent kernel (the
-finest-level Chebyshev smoothing step) from live HIP-event timing of every
-launch in a separate pass over the same step.  `cpu_baseline` times the CPU
+finest-level Chebyshev smoothing step) from HIP events around every run of
+its consecutive launches in a second pass over the same step.  `cpu_baseline` times the CPU
 oracle on a bounded sample (see its `sample` field).
 """
 from __future__ import annotations
@@ -149,6 +149,8 @@ def main():
 
     roof = None
     if not args.no_roofline:
+        # the same step again, kernels launched one by one, each run of
+        # consecutive dominant-kernel launches bracketed by HIP events
         prob.kernel_timer(True)
         run_step(prob, b, D, lams)
         torch.cuda.synchronize()
@@ -159,7 +161,7 @@ def main():
         roof = {"bound": "hbm", "achieved": round(achieved, 1),
                 "peak": HBM_PEAK_GBS, "unit": "GB/s",
                 "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
-                "kernel": "k_apply<PRO_PLAIN, EPI_CHEB> (finest level)",
+                "kernel": "k_smooth_fine (finest-level Chebyshev step)",
                 "launches": launches,
                 "avg_launch_us": round(1e6 * avg_s, 3),
                 "bytes_per_launch": round(nbytes / max(launches, 1))}

@@ -220,12 +220,15 @@ rls_status rls_gershgorin(rls_problem* p, int level, const double* lam,
  * operator with the Chebyshev-step epilogue and a plain prologue (all but
  * two of the 2 nu - 1 finest-level smoothing launches of a V-cycle).  While
  * enabled, rls_solve_sweep launches kernels one by one instead of replaying
- * graphs, and brackets every such launch with a pair of HIP events on the
- * caller's stream.  rls_kernel_timer(p, 1) enables and resets, (p, 0)
- * disables.  rls_kernel_timer_read returns the number of timed launches,
- * their summed duration in seconds and their summed algorithmic bytes: per
- * pixel, 40 bytes per active lambda (read x, f, d; write x, d) plus 24 bytes
- * of shared stencil coefficients, every array counted once. */
+ * graphs, and every run of consecutive such launches (the pre- and the
+ * post-smoothing steps of a V-cycle) is bracketed by one pair of HIP events
+ * on the launch stream.
+ * rls_kernel_timer(p, 1) enables and resets, (p, 0) disables.
+ * rls_kernel_timer_read returns the number of timed launches, their summed
+ * duration in seconds and their summed algorithmic bytes: per pixel, 40
+ * bytes per active lambda (read x, f, d; write x, d) plus, for launches with
+ * an active lambda, 24 bytes of shared stencil coefficients, every array
+ * counted once. */
 rls_status rls_kernel_timer(rls_problem* p, int enable);
 rls_status rls_kernel_timer_read(const rls_problem* p, long long* launches,
                                  double* seconds, double* bytes);

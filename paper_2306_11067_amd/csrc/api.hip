@@ -152,14 +152,20 @@ struct rls_problem {
     hipStream_t cstream = nullptr;   // capture stream for iteration graphs
     // live timing of the finest-level Chebyshev-step kernel
     bool timer_on = false;
-    std::vector<std::pair<hipEvent_t, hipEvent_t>> ev_pool, ev_pending;
-    long long timer_launches = 0, timer_counted = 0;
+    struct TimedRun {
+        hipEvent_t a = nullptr, b = nullptr;
+        int launches = 0;
+    };
+    std::vector<TimedRun> run_pool;      // free event pairs
+    std::vector<TimedRun> run_pending;   // recorded, not yet read
+    TimedRun run_cur;
+    long long timer_launches = 0;
     double timer_seconds = 0.0, timer_bytes = 0.0;
     int kt = 0;                      // first level handled by the tail kernel
     int64_t n() const { return (int64_t)nv * nh; }
     ~rls_problem() {
-        for (auto& e : ev_pool) { hipEventDestroy(e.first); hipEventDestroy(e.second); }
-        for (auto& e : ev_pending) { hipEventDestroy(e.first); hipEventDestroy(e.second); }
+        for (auto* v : {&run_pool, &run_pending})
+            for (auto& e : *v) { hipEventDestroy(e.a); hipEventDestroy(e.b); }
         if (cstream) hipStreamDestroy(cstream);
     }
 };
@@ -179,34 +185,49 @@ rls_status check_launch(const char* where) {
     return RLS_OK;
 }
 
-// Timed launch of the finest-level Chebyshev-step kernel.
-void timed_apply(rls_problem* P, int pro, int epi, const ApplyArgs& a,
-                 hipStream_t s) {
-    std::pair<hipEvent_t, hipEvent_t> ev;
-    if (P->ev_pool.empty()) {
-        hipEventCreate(&ev.first);
-        hipEventCreate(&ev.second);
-    } else {
-        ev = P->ev_pool.back();
-        P->ev_pool.pop_back();
+// Finest-level Chebyshev steps come in runs of consecutive launches (the
+// pre- and the post-smoothing steps of a V-cycle).  With the kernel timer
+// on (direct launches only), each run is bracketed by one pair of HIP
+// events on the launch stream, so the event time is that of the kernels
+// back to back and not of the dispatch of each one.
+void run_begin(rls_problem* P, hipStream_t s) {
+    if (!P->timer_on) return;
+    if (P->run_pool.empty()) {
+        rls_problem::TimedRun r;
+        hipEventCreate(&r.a);
+        hipEventCreate(&r.b);
+        P->run_pool.push_back(r);
     }
-    hipEventRecord(ev.first, s);
-    launch_apply(pro, epi, a, s);
-    hipEventRecord(ev.second, s);
-    P->ev_pending.push_back(ev);
+    P->run_cur = P->run_pool.back();
+    P->run_pool.pop_back();
+    P->run_cur.launches = 0;
+    hipEventRecord(P->run_cur.a, s);
 }
 
-// Fold completed event pairs into the timer totals (stream synchronized).
+void smooth_fine(rls_problem* P, const ApplyArgs& a, hipStream_t s) {
+    launch_smooth_fine(a, s);
+    if (P->timer_on) P->run_cur.launches += 1;
+}
+
+void run_end(rls_problem* P, hipStream_t s) {
+    if (!P->timer_on) return;
+    hipEventRecord(P->run_cur.b, s);
+    P->run_pending.push_back(P->run_cur);
+}
+
+// After a stream synchronization: fold the timed runs into the totals.
 void drain_timer(rls_problem* P) {
-    for (auto& ev : P->ev_pending) {
+    for (auto& r : P->run_pending) {
         float ms = 0.f;
-        if (hipEventElapsedTime(&ms, ev.first, ev.second) == hipSuccess) {
+        if (hipEventElapsedTime(&ms, r.a, r.b) == hipSuccess) {
             P->timer_seconds += 1e-3 * ms;
-            P->timer_launches += 1;
+            P->timer_launches += r.launches;
+        } else {
+            (void)hipGetLastError();   // not a launch error: do not keep it
         }
-        P->ev_pool.push_back(ev);
+        P->run_pool.push_back(r);
     }
-    P->ev_pending.clear();
+    P->run_pending.clear();
 }
 
 rls_status ensure_work(rls_problem* P, int nslot) {
@@ -556,15 +577,17 @@ void vcycle(rls_problem* P, int k, int nslot, const int* slots,
         j.cheb = cheb + 2;
         launch_apply(PRO_JACOBI, EPI_CHEB, j, s);   // x1 = c f / diag, step 2
     }
+    if (top && nu > 2) run_begin(P, s);
     for (int st = 2; st < nu; ++st) {
         ApplyArgs c = a;
         c.in = bufs[cur];
         c.out = bufs[1 - cur];
         c.cheb = cheb + 2 * st;
-        if (top && P->timer_on) timed_apply(P, PRO_PLAIN, EPI_CHEB, c, s);
+        if (top) smooth_fine(P, c, s);
         else launch_apply(PRO_PLAIN, EPI_CHEB, c, s);
         cur = 1 - cur;
     }
+    if (top && nu > 2) run_end(P, s);
     {
         ApplyArgs r = a;                            // residual + restriction
         r.in = bufs[cur];
@@ -583,8 +606,10 @@ void vcycle(rls_problem* P, int k, int nslot, const int* slots,
             c.part = ctl.dot_part;
             c.part_stride = ctl.dot_stride;
         }
-        if (top && st > 0 && P->timer_on) timed_apply(P, PRO_PLAIN, EPI_CHEB, c, s);
+        if (top && st == 1) run_begin(P, s);
+        if (top && st > 0) smooth_fine(P, c, s);
         else launch_apply(st == 0 ? PRO_PROLONG : PRO_PLAIN, EPI_CHEB, c, s);
+        if (top && st > 0 && st == nu - 1) run_end(P, s);
         cur = 1 - cur;
     }
 }
@@ -786,7 +811,7 @@ rls_status rls_vcycle(rls_problem* p, const double* lam, int nlam,
 rls_status rls_kernel_timer(rls_problem* p, int enable) {
     if (!p) return fail(RLS_E_STATE, "null handle");
     p->timer_on = enable != 0;
-    p->timer_launches = p->timer_counted = 0;
+    p->timer_launches = 0;
     p->timer_seconds = p->timer_bytes = 0.0;
     return RLS_OK;
 }
@@ -1029,14 +1054,20 @@ rls_status rls_solve_sweep(rls_problem* p, const double* b, const double* lam,
     RLS_HIP(hipStreamSynchronize(s));
     if (p->timer_on) {
         drain_timer(p);
-        // every V-cycle of a slot takes part in 2 nu - 3 timed launches
+        // Every V-cycle of a slot takes part in 2 nu - 3 finest-level
+        // Chebyshev-step launches (40 bytes per pixel per slot); a launch
+        // with at least one active slot also reads the three shared stencil
+        // planes (24 bytes per pixel).
         const int nu0 = p->nu[0];
-        const int per_cycle = (p->levels > 1 && p->kt > 0 && nu0 >= 2) ? 2 * nu0 - 3 : 0;
+        const int per_cycle = (p->kt > 0 && nu0 >= 2) ? 2 * nu0 - 3 : 0;
         double slot_launches = 0.0;
-        for (int i = 0; i < ns; ++i) slot_launches += (double)hst[i].ncycle * per_cycle;
-        p->timer_bytes += (double)n * (40.0 * slot_launches) +
-                          (double)n * 24.0 * (double)(p->timer_launches - p->timer_counted);
-        p->timer_counted = p->timer_launches;
+        int max_cycles = 0;
+        for (int i = 0; i < ns; ++i) {
+            slot_launches += (double)hst[i].ncycle * per_cycle;
+            max_cycles = std::max(max_cycles, hst[i].ncycle);
+        }
+        p->timer_bytes += (double)n * 40.0 * slot_launches +
+                          (double)n * 24.0 * (double)max_cycles * per_cycle;
     }
     for (int i = 0; i < ns; ++i) {
         if (resnorm) resnorm[i] = std::sqrt(h3[ns + i]);

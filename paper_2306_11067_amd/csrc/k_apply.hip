@@ -126,10 +126,57 @@ __device__ __forceinline__ void vert_window(const double* __restrict__ vin,
     }
 }
 
+// Per-output operands of the epilogue, loaded from global memory before
+// the tile's barriers so that their latency overlaps the tile load.
+struct OutPre {
+    bool ok;
+    int gi, gj;
+    double sc, sn, snm, se, sem, sne, snem, sse, ssep;   // stencil couplings
+    double f, d, dg;                                    // rhs, direction, diag
+};
+
 template <int PRO, int EPI>
-__global__ void __launch_bounds__(APPLY_THREADS) k_apply(ApplyArgs a) {
-    extern __shared__ double lds[];
-    __shared__ double red[APPLY_THREADS];
+__device__ __forceinline__ void out_load(OutPre& q, int e, const ApplyArgs& a,
+                                         const TileShape& T, int i0, int j0,
+                                         size_t so, double l2) {
+    const LevelGeom& g = a.g;
+    const int nv = g.nv, nh = g.nh, per = g.S.periodic;
+    const int c = e / T.RO, r = e - c * T.RO;
+    int gi = i0 + r - T.lo, gj = j0 + c - T.lo;
+    q.ok = gi < nv && (gi >= 0 || per) && gj < nh && (gj >= 0 || per);
+    if (!q.ok) return;
+    if (gi < 0) gi += nv;
+    if (gj < 0) gj += nh;
+    q.gi = gi;
+    q.gj = gj;
+    const int64_t p = gi + (int64_t)nv * gj;
+    int im = gi - 1, jm = gj - 1, ip = gi + 1;
+    const bool okim = wrap_or_drop(im, nv, per);
+    const bool okjm = wrap_or_drop(jm, nh, per);
+    const bool okip = wrap_or_drop(ip, nv, per);
+    q.sc = g.S.c[p];
+    q.sn = g.S.cn[p];
+    q.snm = okim ? g.S.cn[im + (int64_t)nv * gj] : 0.0;
+    q.se = g.S.ce[p];
+    q.sem = okjm ? g.S.ce[gi + (int64_t)nv * jm] : 0.0;
+    if (g.S.nine) {
+        q.sne = g.S.cne[p];
+        q.snem = (okim && okjm) ? g.S.cne[im + (int64_t)nv * jm] : 0.0;
+        q.sse = g.S.cse[p];
+        q.ssep = (okip && okjm) ? g.S.cse[ip + (int64_t)nv * jm] : 0.0;
+    }
+    const size_t o = so + p;
+    if (EPI == EPI_RESID || EPI == EPI_RESTRICT || EPI == EPI_CHEB)
+        q.f = a.f[a.f_shared ? p : o];
+    if (EPI == EPI_CHEB) {
+        q.d = PRO == PRO_JACOBI ? 0.0 : a.d[o];
+        q.dg = g.gv.diag[gi] * g.gh.diag[gj] + l2 * q.sc;
+    }
+}
+
+template <int PRO, int EPI>
+__device__ __forceinline__ void apply_body(const ApplyArgs& a, double* lds,
+                                           double* red) {
     constexpr int EXT = EPI == EPI_RESTRICT ? 1 : 0;
     const int slot = a.slots ? a.slots[blockIdx.z] : (int)blockIdx.z;
     if (a.active && !a.active[slot]) return;
@@ -171,6 +218,12 @@ __global__ void __launch_bounds__(APPLY_THREADS) k_apply(ApplyArgs a) {
     }
     if (PRO == PRO_JACOBI || PRO == PRO_PROLONG_JAC)
         cj = a.cheb_first[(size_t)slot * a.cheb_stride + 1];
+
+    // 0. operands of this thread's first output, in flight during the load
+    OutPre pre;
+    const int nout = T.RO * T.CO;
+    if ((int)threadIdx.x < nout)
+        out_load<PRO, EPI>(pre, threadIdx.x, a, T, i0, j0, so, l2);
 
     // 1. stage band coefficients, load v with prologue
     for (int e = threadIdx.x; e < T.NCV * T.WVP; e += APPLY_THREADS) {
@@ -251,17 +304,15 @@ __global__ void __launch_bounds__(APPLY_THREADS) k_apply(ApplyArgs a) {
 
     // 3.-5. horizontal pass, stencil, epilogue
     double dot = 0.0;
-    for (int e = threadIdx.x; e < T.RO * T.CO; e += APPLY_THREADS) {
+    for (int e = threadIdx.x; e < nout; e += APPLY_THREADS) {
         const int c = e / T.RO, r = e - c * T.RO;          // local + lo
-        int gi = i0 + r - T.lo, gj = j0 + c - T.lo;
-        const bool okr = gi < nv && (gi >= 0 || per);
-        const bool okc = gj < nh && (gj >= 0 || per);
-        if (!okr || !okc) {
+        OutPre q;
+        if (e == (int)threadIdx.x) q = pre;
+        else out_load<PRO, EPI>(q, e, a, T, i0, j0, so, l2);
+        if (!q.ok) {
             if (EXT) rs[c * T.SR + r] = 0.0;
             continue;
         }
-        if (gi < 0) gi += nv;
-        if (gj < 0) gj += nh;
         double kv = 0.0;
         {
             const double* row = vt + (c - T.lo + T.hh - bwh) * T.SO + r;
@@ -270,43 +321,37 @@ __global__ void __launch_bounds__(APPLY_THREADS) k_apply(ApplyArgs a) {
             for (int k = 0; k < T.WH; ++k) kv += cf[k] * row[k * T.SO];
         }
         const double* vc = vin + (c - T.lo + T.hh) * T.SY + r - T.lo + T.hv;
-        const int64_t p = gi + (int64_t)nv * gj;
-        int im = gi - 1, jm = gj - 1, ip = gi + 1;
-        const bool okim = wrap_or_drop(im, nv, per);
-        const bool okjm = wrap_or_drop(jm, nh, per);
-        const bool okip = wrap_or_drop(ip, nv, per);
-        double sv = g.S.c[p] * vc[0];
-        sv += g.S.cn[p] * vc[1];
-        if (okim) sv += g.S.cn[im + (int64_t)nv * gj] * vc[-1];
-        sv += g.S.ce[p] * vc[T.SY];
-        if (okjm) sv += g.S.ce[gi + (int64_t)nv * jm] * vc[-T.SY];
+        double sv = q.sc * vc[0];
+        sv += q.sn * vc[1];
+        sv += q.snm * vc[-1];
+        sv += q.se * vc[T.SY];
+        sv += q.sem * vc[-T.SY];
         if (g.S.nine) {
-            sv += g.S.cne[p] * vc[T.SY + 1];
-            if (okim && okjm) sv += g.S.cne[im + (int64_t)nv * jm] * vc[-T.SY - 1];
-            sv += g.S.cse[p] * vc[T.SY - 1];
-            if (okip && okjm) sv += g.S.cse[ip + (int64_t)nv * jm] * vc[-T.SY + 1];
+            sv += q.sne * vc[T.SY + 1];
+            sv += q.snem * vc[-T.SY - 1];
+            sv += q.sse * vc[T.SY - 1];
+            sv += q.ssep * vc[-T.SY + 1];
         }
         kv += l2 * sv;
         const double v = vc[0];
-        const size_t o = so + p;
+        const size_t o = so + q.gi + (int64_t)nv * q.gj;
         if (EPI == EPI_STORE) {
             a.out[o] = kv;
         } else if (EPI == EPI_DOT) {
             a.out[o] = kv;
             dot += v * kv;
         } else if (EPI == EPI_RESID) {
-            a.out[o] = a.f[a.f_shared ? p : o] - kv;
+            a.out[o] = q.f - kv;
         } else if (EPI == EPI_RESTRICT) {
-            rs[c * T.SR + r] = a.f[a.f_shared ? p : o] - kv;
+            rs[c * T.SR + r] = q.f - kv;
         } else {   // EPI_CHEB
-            const double f = a.f[a.f_shared ? p : o];
             const double* cc = a.cheb + (size_t)slot * a.cheb_stride;
-            const double dprev = PRO == PRO_JACOBI ? v : a.d[o];
-            const double dn = cc[0] * dprev + cc[1] * (f - kv) / diag_at(g, l2, gi, gj, p);
+            const double dprev = PRO == PRO_JACOBI ? v : q.d;
+            const double dn = cc[0] * dprev + cc[1] * (q.f - kv) / q.dg;
             a.d[o] = dn;
             const double xn = v + dn;
             a.out[o] = xn;
-            if (a.dot) dot += f * xn;
+            if (a.dot) dot += q.f * xn;
         }
     }
     if (EPI == EPI_RESTRICT) {
@@ -344,6 +389,22 @@ __global__ void __launch_bounds__(APPLY_THREADS) k_apply(ApplyArgs a) {
         if (threadIdx.x == 0)
             a.part[(size_t)slot * a.part_stride + tile] = s;
     }
+}
+
+template <int PRO, int EPI>
+__global__ void __launch_bounds__(APPLY_THREADS) k_apply(ApplyArgs a) {
+    extern __shared__ double lds[];
+    __shared__ double red[APPLY_THREADS];
+    apply_body<PRO, EPI>(a, lds, red);
+}
+
+// The finest-level Chebyshev step (plain prologue) under a name of its own,
+// so that profiles separate the sweep's most frequent kernel from the same
+// step on coarser levels.
+__global__ void __launch_bounds__(APPLY_THREADS) k_smooth_fine(ApplyArgs a) {
+    extern __shared__ double lds[];
+    __shared__ double red[APPLY_THREADS];
+    apply_body<PRO_PLAIN, EPI_CHEB>(a, lds, red);
 }
 
 template <int PRO, int EPI>
@@ -387,6 +448,15 @@ void configure_apply_kernels() {
 #define RLS_CFG(P, E) configure_one<P, E>();
     RLS_APPLY_VARIANTS(RLS_CFG)
 #undef RLS_CFG
+    {
+        hipFuncAttributes attr;
+        size_t stat = 0;
+        if (hipFuncGetAttributes(&attr, (const void*)k_smooth_fine) == hipSuccess)
+            stat = attr.sharedSizeBytes;
+        (void)hipFuncSetAttribute((const void*)k_smooth_fine,
+                                  hipFuncAttributeMaxDynamicSharedMemorySize,
+                                  (int)(160 * 1024 - stat));
+    }
     (void)hipGetLastError();
     done = true;
 }
@@ -398,6 +468,14 @@ int apply_tiles(const LevelGeom& g) {
 size_t apply_lds_bytes(const LevelGeom& g, int epi) {
     const TileShape T(g, epi == EPI_RESTRICT);
     return sizeof(double) * T.lds_doubles(epi == EPI_RESTRICT);
+}
+
+void launch_smooth_fine(const ApplyArgs& a, hipStream_t s) {
+    const TileShape T(a.g, 0);
+    dim3 grid((a.g.nv + TILE_Y - 1) / TILE_Y, (a.g.nh + TILE_X - 1) / TILE_X,
+              a.nslot);
+    hipLaunchKernelGGL(k_smooth_fine, grid, dim3(APPLY_THREADS),
+                       sizeof(double) * T.lds_doubles(0), s, a);
 }
 
 void launch_apply(int pro, int epi, const ApplyArgs& a, hipStream_t s) {

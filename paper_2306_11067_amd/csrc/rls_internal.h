@@ -121,6 +121,9 @@ struct ApplyArgs {
 
 void launch_apply(int pro, int epi, const ApplyArgs& a, hipStream_t s);
 void configure_apply_kernels();  // LDS limits of every variant, once
+// Finest-level Chebyshev step (plain prologue): same arithmetic as
+// launch_apply(PRO_PLAIN, EPI_CHEB), distinct kernel name.
+void launch_smooth_fine(const ApplyArgs& a, hipStream_t s);
 
 // ---- setup kernels (k_setup.hip) ------------------------------------
 void launch_blur_band(const double* taps, int r, int n, int bc, double* band,

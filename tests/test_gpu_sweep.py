@@ -142,3 +142,29 @@ def test_graph_replay_equals_direct_launches():
         assert np.array_equal(host(xg), host(xd))
         assert [i["iters"] for i in ig] == [i["iters"] for i in idd]
         assert np.array_equal(rg, rd) and np.array_equal(sg, sd)
+
+
+def test_kernel_timer_counts_finest_smoothing_launches():
+    # With the timer on, every finest-level Chebyshev-step launch is timed;
+    # results are bitwise those of the graph-replayed sweep, and the bytes
+    # follow the per-launch model n * (40 * active + 24).
+    from paper_2306_11067_amd import Problem
+    P_ = W.small_deblur(128, 96, 3, 1.5, "reflective", "neumann", 3, nlam=3)
+    nu = 5
+    prob = Problem(P_.nv, P_.nh, P_.taps_v, P_.taps_h, P_.bc, P_.lbc,
+                   P_.levels, nu=nu, cheb_ratio=30.0, nu_coarse=2,
+                   cheb_ratio_coarse=4.0, weights=dev(P_.weights[1]))
+    b = dev(P_.b)
+    x0, _, _, i0 = prob.solve_sweep(b, P_.lams, 1e-10)
+    prob.kernel_timer(True)
+    x1, _, _, i1 = prob.solve_sweep(b, P_.lams, 1e-10, poll_every=4)
+    launches, seconds, nbytes = prob.kernel_timer_read()
+    prob.kernel_timer(False)
+    assert np.array_equal(host(x0), host(x1))
+    n = P_.nv * P_.nh
+    cycles = [i["iters"] + 1 for i in i1]     # gate passes + initial cycle
+    assert launches >= max(cycles) * (2 * nu - 3)
+    assert seconds > 0
+    lo = n * 40.0 * (2 * nu - 3) * sum(cycles) * 0.5
+    hi = n * (40.0 * len(cycles) + 24.0) * launches
+    assert lo <= nbytes <= hi, (lo, nbytes, hi)
