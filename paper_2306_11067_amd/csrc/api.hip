@@ -671,6 +671,24 @@ rls_status rls_setup(rls_problem** out, const rls_op_desc* A,
         return fail(RLS_E_UNSUPPORTED,
                     "supported (blur, gradient) boundary pairs: (periodic, "
                     "periodic), (reflective, neumann), (zero, neumann)");
+    if ((int64_t)g->nv * g->nh > (int64_t)1 << 28)
+        return fail(RLS_E_UNSUPPORTED, "grids are limited to 2^28 points");
+    {
+        // the finest level has the widest Gram bands (half-width 2r); its
+        // restriction tile with per-row coefficients is the largest LDS user
+        LevelGeom g0;
+        g0.nv = g->nv;
+        g0.nh = g->nh;
+        g0.gv.bw = 2 * A->r_v;
+        g0.gh.bw = 2 * A->r_h;
+        const size_t need = apply_lds_bytes(g0, EPI_RESTRICT);
+        const size_t have = 160 * 1024 - sizeof(double) * APPLY_THREADS;
+        if (need > have)
+            return fail(RLS_E_UNSUPPORTED,
+                        "blur radius too large for the level-operator tile: "
+                        "needs " + std::to_string(need) + " bytes of LDS, " +
+                        std::to_string(have) + " available");
+    }
     std::unique_ptr<rls_problem> P(new rls_problem());
     RLS_HIP(hipGetDevice(&P->device));
     RLS_HIP(hipStreamCreateWithFlags(&P->cstream, hipStreamNonBlocking));

@@ -1,14 +1,20 @@
 // Level operator K_k(lambda) v = (G_h (x) G_v) v + lambda^2 S_k v, batched
 // over lambda, with a fused prologue (how v is formed while it is loaded)
-// and epilogue (what is done with K v).  One workgroup computes one output
-// tile of one lambda slot:
+// and epilogue (what is done with K v).  One 256-thread workgroup computes
+// one 64 x 16 output tile of one lambda slot (about 50 KB of LDS, so three
+// workgroups share a CU and one's loads overlap another's arithmetic):
+//   0. issue the global loads of the per-output operands (right-hand side,
+//      direction, stencil couplings);
 //   1. load v on the tile plus a halo into LDS (the Gram band's index map
 //      supplies wrap / reflection / zero outside the grid), applying the
-//      prologue at every loaded point; stage the band coefficients in LDS;
-//   2. vertical pass of G_v for every loaded column;
-//   3. horizontal pass of G_h;
-//   4. add lambda^2 times the 9-point stencil S_k read from the LDS tile;
-//   5. epilogue.
+//      prologue at every loaded point; stage the band coefficients;
+//   2. horizontal pass of G_h over the output columns and the extended
+//      rows (register windows of 8 columns);
+//   3. vertical pass of G_v over the output rows (windows of 8 rows);
+//   4. add lambda^2 times the 9-point stencil S_k read from the LDS tile and
+//      apply the epilogue, lanes along the contiguous axis.
+// The horizontal pass runs first because the tile is taller than wide: the
+// first pass is evaluated on the halo of the second, 92 rows for 64 here.
 // This is the two-stage level product of the paper's Section 3.2: for the
 // blur the products with A_k and A_k^T collapse into the separable Gram
 // A_k^T A_k = G_h (x) G_v, and M_k^T M_k is the Galerkin stencil of
@@ -22,9 +28,11 @@
 
 namespace rls {
 
+__device__ __forceinline__ double ldu(const double* base, uint32_t idx);
+
 __device__ __forceinline__ double diag_at(const LevelGeom& g, double l2,
-                                          int i, int j, int64_t p) {
-    return g.gv.diag[i] * g.gh.diag[j] + l2 * g.S.c[p];
+                                          int i, int j, uint32_t p) {
+    return g.gv.diag[i] * g.gh.diag[j] + l2 * ldu(g.S.c, p);
 }
 
 // Coarse points contributing to fine point f and their weights (linear
@@ -57,120 +65,196 @@ __device__ __forceinline__ double prolong_at(const double* __restrict__ e,
     return s;
 }
 
-// Register window of the vertical pass for uniform bands: each thread
-// produces VWIN consecutive rows of one column, consuming the taps VCH at
-// a time (taps zero-padded to a multiple of VCH).
+// Register windows of the two band passes: a thread produces HWIN (VWIN)
+// consecutive outputs of one row (column), consuming the taps CH at a time.
+// Tap lists are zero-padded to a multiple of CH, and the LDS lines the
+// padded taps reach are zero-filled, so no undefined value enters a sum.
+constexpr int HWIN = 8;
 constexpr int VWIN = 8;
-constexpr int VCH = 8;
+constexpr int CH = 8;
+// outputs whose operands a thread loads before the tile (every tile has at
+// least TILE_Y * TILE_X outputs)
+constexpr int NPRE = TILE_Y * TILE_X / APPLY_THREADS;
+static_assert(NPRE * APPLY_THREADS == TILE_Y * TILE_X, "tile / block mismatch");
+static_assert((TILE_X + 1) * ((TILE_Y + VWIN) / VWIN) <= APPLY_THREADS,
+              "one vertical window per thread");
 
+__host__ __device__ constexpr int round_up(int x, int m) {
+    return (x + m - 1) / m * m;
+}
+
+// Geometry of one tile.  Output point (r, c), r in [0, RO), c in [0, CO),
+// is grid point (i0 + r - lo, j0 + c - lo); lo = 1 adds the low row and
+// column the full-weighting restriction needs.  The input tile holds v on
+// rows ii in [0, RY) <-> i0 - hv + ii and columns jj in [0, CX) <->
+// j0 - hh + jj, row-major with row stride SX (odd: conflict-free when
+// lanes run along rows).
 struct TileShape {
-    int lo, hv, hh, RY, SY, CX, SO, RO, CO, SR, WV, WVP, WH, NCV, NCH;
+    int lo, bwv, bwh, hv, hh;
+    int RY, CX, SX;         // input rows, columns, row stride (>= CX)
+    int RO, CO;             // output rows / columns
+    int NWH, NWV;           // windows per output row / column
+    int NHR, SH;            // rows of the horizontal-pass result, stride
+    int SR;                 // column stride of the staged K v
+    int WV, WVP, WH, WHP;   // tap counts, padded to CH
+    int NCV, NCH;           // staged coefficient lines (1: uniform band)
     __host__ __device__ TileShape(const LevelGeom& g, int ext) {
         lo = ext;
-        hv = (g.gv.bw > 1 ? g.gv.bw : 1) + lo;
-        hh = (g.gh.bw > 1 ? g.gh.bw : 1) + lo;
+        bwv = g.gv.bw;
+        bwh = g.gh.bw;
+        hv = (bwv > 1 ? bwv : 1) + lo;
+        hh = (bwh > 1 ? bwh : 1) + lo;
         RY = TILE_Y + 2 * hv;
-        SY = (RY + VWIN + VCH) | 1;   // slack rows read by the last window
         CX = TILE_X + 2 * hh;
-        RO = TILE_Y + lo;             // output rows (incl. low extension)
+        RO = TILE_Y + lo;
         CO = TILE_X + lo;
-        SO = RO | 1;
+        WV = 2 * bwv + 1;
+        WVP = round_up(WV, CH);
+        WH = 2 * bwh + 1;
+        WHP = round_up(WH, CH);
+        NWH = (CO + HWIN - 1) / HWIN;
+        NWV = (RO + VWIN - 1) / VWIN;
+        // one past the last input column a horizontal window reads
+        const int cend = NWH * HWIN + WHP - 1 - lo + hh - bwh;
+        SX = (cend > CX ? cend : CX) | 1;
+        NHR = RO + 2 * bwv;
+        SH = (NWV * VWIN + WVP - 1) | 1;
         SR = RO | 1;
-        WV = 2 * g.gv.bw + 1;
-        WVP = (WV + VCH - 1) / VCH * VCH;
-        WH = 2 * g.gh.bw + 1;
-        NCV = g.gv.uniform ? 1 : RO;  // staged coefficient rows
-        NCH = g.gh.uniform ? 1 : CO;
+        NCV = g.gv.uniform ? 1 : NWV * VWIN;
+        NCH = g.gh.uniform ? 1 : NWH * HWIN;
     }
-    __host__ __device__ size_t lds_doubles(int restrict_) const {
-        return (size_t)CX * SY + (size_t)CX * SO +
-               (restrict_ ? (size_t)CO * SR : 0) + (size_t)NCV * WVP +
-               (size_t)NCH * WH;
+    // the horizontal-pass result, reused for K v (and the residual)
+    __host__ __device__ size_t ht_doubles() const {
+        const size_t x = (size_t)CO * SH, y = (size_t)CO * SR;
+        return x > y ? x : y;
+    }
+    __host__ __device__ size_t lds_doubles() const {
+        return (size_t)RY * SX + ht_doubles() + (size_t)NCV * WVP +
+               (size_t)NCH * WHP + RO + CO;
     }
 };
 
-// Vertical pass of a uniform band with the chunked register window.
-__device__ __forceinline__ void vert_window(const double* __restrict__ vin,
-                                            double* __restrict__ vt,
-                                            const double* __restrict__ taps,
-                                            const TileShape& T, int bw, int i0,
-                                            int nv, int per) {
-    const int nseg = (T.RO + VWIN - 1) / VWIN;
-    for (int e = threadIdx.x; e < nseg * T.CX; e += APPLY_THREADS) {
-        const int sg = e / T.CX, jj = e - sg * T.CX;   // lanes along columns
-        const int r0 = sg * VWIN;
-        const double* col = vin + jj * T.SY + r0 - T.lo + T.hv - bw;
-        double acc[VWIN];
-#pragma unroll
-        for (int o = 0; o < VWIN; ++o) acc[o] = 0.0;
-        for (int c0 = 0; c0 < T.WVP; c0 += VCH) {
-            double win[VWIN + VCH - 1];
-            double tp[VCH];
-#pragma unroll
-            for (int m = 0; m < VWIN + VCH - 1; ++m) win[m] = col[c0 + m];
-#pragma unroll
-            for (int k = 0; k < VCH; ++k) tp[k] = taps[c0 + k];
-#pragma unroll
-            for (int k = 0; k < VCH; ++k)
-#pragma unroll
-                for (int o = 0; o < VWIN; ++o) acc[o] += tp[k] * win[o + k];
-        }
-#pragma unroll
-        for (int o = 0; o < VWIN; ++o) {
-            const int r = r0 + o;
-            if (r >= T.RO) break;
-            const int gi = i0 + r - T.lo;
-            const bool ok = gi < nv && (gi >= 0 || per);
-            vt[jj * T.SO + r] = ok ? acc[o] : 0.0;
-        }
-    }
+// Grid point of output e, false outside the grid.
+__device__ __forceinline__ bool out_index(int e, const TileShape& T,
+                                          const LevelGeom& g, int i0, int j0,
+                                          int& gi, int& gj) {
+    const int nv = g.nv, nh = g.nh, per = g.S.periodic;
+    const int c = e / T.RO, r = e - c * T.RO;
+    gi = i0 + r - T.lo;
+    gj = j0 + c - T.lo;
+    if (!(gi < nv && (gi >= 0 || per) && gj < nh && (gj >= 0 || per)))
+        return false;
+    if (gi < 0) gi += nv;
+    if (gj < 0) gj += nh;
+    return true;
 }
 
-// Per-output operands of the epilogue, loaded from global memory before
-// the tile's barriers so that their latency overlaps the tile load.
+// Element idx of an array with a workgroup-uniform base: a 32-bit byte
+// offset on a scalar base (grids are limited to 2^28 points per slot).
+__device__ __forceinline__ double ldu(const double* base, uint32_t idx) {
+    return *reinterpret_cast<const double*>(
+        reinterpret_cast<const char*>(base) + (idx << 3));
+}
+__device__ __forceinline__ void stu(double* base, uint32_t idx, double v) {
+    *reinterpret_cast<double*>(reinterpret_cast<char*>(base) + (idx << 3)) = v;
+}
+
+// The slot's arrays (uniform over the workgroup).
+struct SlotPtrs {
+    const double* src;   // operand v (or z for the p update)
+    const double* pold;  // previous search direction
+    const double* f;     // right-hand side
+    double* d;           // Chebyshev direction
+    double* out;         // result
+    double* pnew;        // new search direction
+};
+
+// Operands of one output point from global memory, requested before the
+// tile load so that they arrive with it: right-hand side and Chebyshev
+// direction (per lambda) and the five-point part of the stencil (centre,
+// north, south, east, west couplings; zero across a non-periodic edge).
 struct OutPre {
-    bool ok;
-    int gi, gj;
-    double sc, sn, snm, se, sem, sne, snem, sse, ssep;   // stencil couplings
-    double f, d, dg;                                    // rhs, direction, diag
+    double f, d, sc, sn, ss, se, sw;
 };
 
 template <int PRO, int EPI>
 __device__ __forceinline__ void out_load(OutPre& q, int e, const ApplyArgs& a,
-                                         const TileShape& T, int i0, int j0,
-                                         size_t so, double l2) {
+                                         const SlotPtrs& sp, const TileShape& T,
+                                         int i0, int j0) {
     const LevelGeom& g = a.g;
     const int nv = g.nv, nh = g.nh, per = g.S.periodic;
-    const int c = e / T.RO, r = e - c * T.RO;
-    int gi = i0 + r - T.lo, gj = j0 + c - T.lo;
-    q.ok = gi < nv && (gi >= 0 || per) && gj < nh && (gj >= 0 || per);
-    if (!q.ok) return;
-    if (gi < 0) gi += nv;
-    if (gj < 0) gj += nh;
-    q.gi = gi;
-    q.gj = gj;
-    const int64_t p = gi + (int64_t)nv * gj;
-    int im = gi - 1, jm = gj - 1, ip = gi + 1;
+    q.f = q.d = q.sc = q.sn = q.ss = q.se = q.sw = 0.0;
+    int gi, gj;
+    if (!out_index(e, T, g, i0, j0, gi, gj)) return;
+    const uint32_t p = gi + (uint32_t)nv * gj;
+    int im = gi - 1, jm = gj - 1;
     const bool okim = wrap_or_drop(im, nv, per);
     const bool okjm = wrap_or_drop(jm, nh, per);
-    const bool okip = wrap_or_drop(ip, nv, per);
-    q.sc = g.S.c[p];
-    q.sn = g.S.cn[p];
-    q.snm = okim ? g.S.cn[im + (int64_t)nv * gj] : 0.0;
-    q.se = g.S.ce[p];
-    q.sem = okjm ? g.S.ce[gi + (int64_t)nv * jm] : 0.0;
-    if (g.S.nine) {
-        q.sne = g.S.cne[p];
-        q.snem = (okim && okjm) ? g.S.cne[im + (int64_t)nv * jm] : 0.0;
-        q.sse = g.S.cse[p];
-        q.ssep = (okip && okjm) ? g.S.cse[ip + (int64_t)nv * jm] : 0.0;
-    }
-    const size_t o = so + p;
+    q.sc = ldu(g.S.c, p);
+    q.sn = ldu(g.S.cn, p);
+    if (okim) q.ss = ldu(g.S.cn, im + (uint32_t)nv * gj);
+    q.se = ldu(g.S.ce, p);
+    if (okjm) q.sw = ldu(g.S.ce, gi + (uint32_t)nv * jm);
     if (EPI == EPI_RESID || EPI == EPI_RESTRICT || EPI == EPI_CHEB)
-        q.f = a.f[a.f_shared ? p : o];
-    if (EPI == EPI_CHEB) {
-        q.d = PRO == PRO_JACOBI ? 0.0 : a.d[o];
-        q.dg = g.gv.diag[gi] * g.gh.diag[gj] + l2 * q.sc;
+        q.f = ldu(sp.f, p);
+    if (EPI == EPI_CHEB && PRO != PRO_JACOBI) q.d = ldu(sp.d, p);
+}
+
+// Stencil term and epilogue at output e; K v's Gram part is staged in kvs.
+template <int PRO, int EPI>
+__device__ __forceinline__ void out_point(const OutPre& q, int e,
+                                          const ApplyArgs& a,
+                                          const SlotPtrs& sp,
+                                          const TileShape& T,
+                                          const double* vin, double* kvs,
+                                          double l2,
+                                          const double* dgl, double c0,
+                                          double c1, int i0, int j0,
+                                          double& dot) {
+    const int c = e / T.RO, r = e - c * T.RO;
+    const LevelGeom& g = a.g;
+    int gi, gj;
+    if (!out_index(e, T, g, i0, j0, gi, gj)) {
+        if (EPI == EPI_RESTRICT) kvs[c * T.SR + r] = 0.0;
+        return;
+    }
+    const int nv = g.nv, nh = g.nh, per = g.S.periodic;
+    const uint32_t p = gi + (uint32_t)nv * gj;
+    const double* vc = vin + (r - T.lo + T.hv) * T.SX + c - T.lo + T.hh;
+    double sv = q.sc * vc[0];
+    sv += q.sn * vc[T.SX];
+    sv += q.ss * vc[-T.SX];
+    sv += q.se * vc[1];
+    sv += q.sw * vc[-1];
+    if (g.S.nine) {
+        int im = gi - 1, jm = gj - 1, ip = gi + 1;
+        const bool okim = wrap_or_drop(im, nv, per);
+        const bool okjm = wrap_or_drop(jm, nh, per);
+        const bool okip = wrap_or_drop(ip, nv, per);
+        sv += ldu(g.S.cne, p) * vc[T.SX + 1];
+        if (okim && okjm) sv += ldu(g.S.cne, im + (uint32_t)nv * jm) * vc[-T.SX - 1];
+        sv += ldu(g.S.cse, p) * vc[-T.SX + 1];
+        if (okip && okjm) sv += ldu(g.S.cse, ip + (uint32_t)nv * jm) * vc[T.SX - 1];
+    }
+    const double kv = kvs[c * T.SR + r] + l2 * sv;
+    const double v = vc[0];
+    if (EPI == EPI_STORE) {
+        stu(sp.out, p, kv);
+    } else if (EPI == EPI_DOT) {
+        stu(sp.out, p, kv);
+        dot += v * kv;
+    } else if (EPI == EPI_RESID) {
+        stu(sp.out, p, q.f - kv);
+    } else if (EPI == EPI_RESTRICT) {
+        kvs[c * T.SR + r] = q.f - kv;
+    } else {   // EPI_CHEB
+        const double dg = dgl[r] * dgl[T.RO + c] + l2 * q.sc;
+        const double dprev = PRO == PRO_JACOBI ? v : q.d;
+        const double dn = c0 * dprev + c1 * (q.f - kv) / dg;
+        stu(sp.d, p, dn);
+        const double xn = v + dn;
+        stu(sp.out, p, xn);
+        if (a.dot) dot += q.f * xn;
     }
 }
 
@@ -178,8 +262,15 @@ template <int PRO, int EPI>
 __device__ __forceinline__ void apply_body(const ApplyArgs& a, double* lds,
                                            double* red) {
     constexpr int EXT = EPI == EPI_RESTRICT ? 1 : 0;
+    constexpr int NT = APPLY_THREADS;
+    const int t = threadIdx.x;
     const int slot = a.slots ? a.slots[blockIdx.z] : (int)blockIdx.z;
-    if (a.active && !a.active[slot]) return;
+    // A slot that stopped inside a replayed chunk is skipped.  Variants
+    // without folded PCG scalars only test the flag once their loads are
+    // in flight (reading a stopped slot is harmless, writing is not).
+    const bool act = !a.active || a.active[slot];
+    constexpr bool SCALARS = PRO == PRO_PUPDATE;
+    if ((SCALARS || a.gate) && !act) return;
     const LevelGeom& g = a.g;
     const int nv = g.nv, nh = g.nh;
     const int64_t n = (int64_t)nv * nh;
@@ -192,14 +283,20 @@ __device__ __forceinline__ void apply_body(const ApplyArgs& a, double* lds,
     const int tx = tile % ntx, ty = tile / ntx;
     const int i0 = tx * TILE_Y, j0 = ty * TILE_X;
     const TileShape T(g, EXT);
-    const int bwv = g.gv.bw, bwh = g.gh.bw;
     double* vin = lds;
-    double* vt = vin + T.CX * T.SY;
-    double* rs = vt + T.CX * T.SO;
-    double* cv = rs + (EXT ? T.CO * T.SR : 0);
-    double* ch = cv + T.NCV * T.WVP;
+    double* ht = vin + (size_t)T.RY * T.SX;
+    double* kvs = ht;                      // after the vertical pass
+    double* cv = ht + T.ht_doubles();
+    double* ch = cv + (size_t)T.NCV * T.WVP;
+    double* dgl = ch + (size_t)T.NCH * T.WHP;   // diag G_v rows, diag G_h cols
     const size_t so = (size_t)slot * n;
-    const double* src = a.in ? a.in + so : nullptr;
+    SlotPtrs sp;
+    sp.src = a.in ? a.in + so : nullptr;
+    sp.pold = a.pold ? a.pold + so : nullptr;
+    sp.f = a.f ? (a.f_shared ? a.f : a.f + so) : nullptr;
+    sp.d = a.d ? a.d + so : nullptr;
+    sp.out = a.out ? a.out + so : nullptr;
+    sp.pnew = a.pnew ? a.pnew + so : nullptr;
     const double l2 = a.lam2[slot];
     const int per = g.S.periodic;
 
@@ -207,161 +304,263 @@ __device__ __forceinline__ void apply_body(const ApplyArgs& a, double* lds,
     const bool lead = tile == 0;
     double beta = 0.0, cj = 0.0;
     if (PRO == PRO_PUPDATE) {
-        if (!pcg_beta<APPLY_THREADS>(a.st, a.active_w, slot, a.part_rz, a.nrz,
-                                     a.parity, lead, red, beta))
+        if (!pcg_beta<NT>(a.st, a.active_w, slot, a.part_rz, a.nrz, a.parity,
+                          lead, red, beta))
             return;
     }
     if (a.gate) {
-        if (!pcg_gate<APPLY_THREADS>(a.st, a.active_w, slot, a.part_rr, a.nrr,
-                                     lead, red))
+        if (!pcg_gate<NT>(a.st, a.active_w, slot, a.part_rr, a.nrr, lead, red))
             return;
     }
     if (PRO == PRO_JACOBI || PRO == PRO_PROLONG_JAC)
         cj = a.cheb_first[(size_t)slot * a.cheb_stride + 1];
+    double c0 = 0.0, c1 = 0.0;
+    if (EPI == EPI_CHEB) {
+        c0 = a.cheb[(size_t)slot * a.cheb_stride];
+        c1 = a.cheb[(size_t)slot * a.cheb_stride + 1];
+    }
 
-    // 0. operands of this thread's first output, in flight during the load
-    OutPre pre;
-    const int nout = T.RO * T.CO;
-    if ((int)threadIdx.x < nout)
-        out_load<PRO, EPI>(pre, threadIdx.x, a, T, i0, j0, so, l2);
-
-    // 1. stage band coefficients, load v with prologue
-    for (int e = threadIdx.x; e < T.NCV * T.WVP; e += APPLY_THREADS) {
-        const int r = e / T.WVP, k = e - r * T.WVP;
-        double c = 0.0;
-        if (k < T.WV) {                           // zero padding to WVP
-            if (g.gv.uniform) {
-                c = g.gv.taps[k];
-            } else {
-                int gi = i0 + r - T.lo;
-                if (gi < 0 && per) gi += nv;
-                if (gi >= 0 && gi < nv) c = g.gv.table[(size_t)gi * T.WV + k];
+    // 1. everything the tile needs from global memory is requested before
+    //    the first LDS write: uniform taps (one per thread), v on the tile
+    //    plus halo with the prologue applied (batches of LB loads per
+    //    thread, no store in between), and the per-output operands of the
+    //    epilogue, which stay in flight through the band passes.
+    double tapv = 0.0, taph = 0.0, dgt = 0.0;
+    if (g.gv.uniform && t < T.WV) tapv = g.gv.taps[t];
+    if (g.gh.uniform && t < T.WH) taph = g.gh.taps[t];
+    if (EPI == EPI_CHEB && t < T.RO + T.CO) {
+        // diagonal of G_v at output row t, of G_h at output column t - RO
+        const bool row = t < T.RO;
+        const int nn = row ? nv : nh;
+        int gx = row ? i0 + t - T.lo : j0 + (t - T.RO) - T.lo;
+        if (gx < 0 && per) gx += nn;
+        if (gx >= 0 && gx < nn) dgt = row ? g.gv.diag[gx] : g.gh.diag[gx];
+    }
+    // Each thread keeps one tile row (lanes along the contiguous axis, the
+    // row's index map evaluated once) and walks every second column; the
+    // loads of a batch of LB columns are issued back to back.
+    constexpr int RL = APPLY_THREADS / 2;
+    constexpr int LB = PRO == PRO_PLAIN || PRO == PRO_PUPDATE ? 24
+                       : PRO == PRO_JACOBI                      ? 12
+                                                                : 6;
+    OutPre pre[NPRE];
+    const int il = t & (RL - 1), jl = t / RL;
+    for (int rb = 0; rb < T.RY; rb += RL) {
+        const int ii = rb + il;
+        const bool rin = ii < T.RY;
+        const int ui = i0 - T.hv + ii;
+        bool okv;
+        const int gi = map_index(ui, nv, g.gv.map, okv);
+        for (int cb = 0; cb < T.CX; cb += 2 * LB) {
+            double v[LB];
+#pragma unroll
+            for (int u = 0; u < LB; ++u) {
+                const int jj = cb + jl + 2 * u;
+                v[u] = 0.0;
+                bool okh;
+                const int gj = map_index(j0 - T.hh + jj, nh, g.gh.map, okh);
+                if (rin && okv && jj < T.CX && okh) {
+                    const uint32_t p = gi + (uint32_t)nv * gj;
+                    if (PRO == PRO_PLAIN) {
+                        v[u] = ldu(sp.src, p);
+                    } else if (PRO == PRO_PUPDATE) {
+                        // p_old is undefined before the first iteration
+                        const double po = beta == 0.0 ? 0.0 : ldu(sp.pold, p);
+                        v[u] = ldu(sp.src, p) + beta * po;
+                    } else if (PRO == PRO_JACOBI) {
+                        v[u] = cj * ldu(sp.f, p) / diag_at(g, l2, gi, gj, p);
+                    } else if (PRO == PRO_PROLONG) {
+                        v[u] = ldu(sp.src, p) +
+                               prolong_at(a.ec + (size_t)slot * (n >> 2), gi, gj,
+                                          nv, nh, per);
+                    } else {   // PRO_PROLONG_JAC
+                        v[u] = cj * ldu(sp.f, p) / diag_at(g, l2, gi, gj, p) +
+                               prolong_at(a.ec + (size_t)slot * (n >> 2), gi, gj,
+                                          nv, nh, per);
+                    }
+                }
+            }
+            if (rb == 0 && cb == 0) {
+#pragma unroll
+                for (int k = 0; k < NPRE; ++k)
+                    out_load<PRO, EPI>(pre[k], t + k * NT, a, sp, T, i0, j0);
+            }
+#pragma unroll
+            for (int u = 0; u < LB; ++u) {
+                const int jj = cb + jl + 2 * u;
+                if (rin && jj < T.CX) {
+                    vin[ii * T.SX + jj] = v[u];
+                    if (PRO == PRO_PUPDATE) {
+                        // p_new on the tile's own points
+                        const int uj = j0 - T.hh + jj;
+                        const bool own = ii >= T.hv && ii < T.hv + TILE_Y &&
+                                         jj >= T.hh && jj < T.hh + TILE_X &&
+                                         ui < nv && uj < nh;
+                        if (own) stu(sp.pnew, ui + (uint32_t)nv * uj, v[u]);
+                    }
+                }
             }
         }
-        cv[e] = c;
     }
-    for (int e = threadIdx.x; e < T.NCH * T.WH; e += APPLY_THREADS) {
-        const int c0 = e / T.WH, k = e - c0 * T.WH;
-        double c = 0.0;
-        if (g.gh.uniform) {
-            c = g.gh.taps[k];
-        } else {
+
+    if (!SCALARS && !a.gate && !act) return;
+    if (EPI == EPI_CHEB && t < T.RO + T.CO) dgl[t] = dgt;
+
+    // band coefficients (zero-padded to a multiple of CH), zero padding of
+    // the LDS lines the padded taps reach
+    if (g.gv.uniform) {
+        if (t < T.WVP) cv[t] = tapv;
+    } else {
+        for (int e = t; e < T.NCV * T.WVP; e += NT) {
+            const int r = e / T.WVP, k = e - r * T.WVP;
+            int gi = i0 + r - T.lo;
+            if (gi < 0 && per) gi += nv;
+            double c = 0.0;
+            if (k < T.WV && r < T.RO && gi >= 0 && gi < nv)
+                c = g.gv.table[(size_t)gi * T.WV + k];
+            cv[e] = c;
+        }
+    }
+    if (g.gh.uniform) {
+        if (t < T.WHP) ch[t] = taph;
+    } else {
+        for (int e = t; e < T.NCH * T.WHP; e += NT) {
+            const int c0 = e / T.WHP, k = e - c0 * T.WHP;
             int gj = j0 + c0 - T.lo;
             if (gj < 0 && per) gj += nh;
-            if (gj >= 0 && gj < nh) c = g.gh.table[(size_t)gj * T.WH + k];
+            double c = 0.0;
+            if (k < T.WH && c0 < T.CO && gj >= 0 && gj < nh)
+                c = g.gh.table[(size_t)gj * T.WH + k];
+            ch[e] = c;
         }
-        ch[e] = c;
     }
-    for (int e = threadIdx.x; e < T.CX * T.RY; e += APPLY_THREADS) {
-        const int jj = e / T.RY, ii = e - jj * T.RY;
-        const int ui = i0 - T.hv + ii, uj = j0 - T.hh + jj;
-        bool okv, okh;
-        const int gi = map_index(ui, nv, g.gv.map, okv);
-        const int gj = map_index(uj, nh, g.gh.map, okh);
-        double v = 0.0;
-        if (okv && okh) {
-            const int64_t p = gi + (int64_t)nv * gj;
-            if (PRO == PRO_PLAIN) {
-                v = src[p];
-            } else if (PRO == PRO_PUPDATE) {
-                const double po = beta == 0.0 ? 0.0 : a.pold[so + p];
-                v = src[p] + beta * po;
-                const bool own = ii >= T.hv && ii < T.hv + TILE_Y &&
-                                 jj >= T.hh && jj < T.hh + TILE_X && ui < nv &&
-                                 uj < nh;
-                if (own) a.pnew[so + p] = v;
-            } else if (PRO == PRO_JACOBI) {
-                v = cj * a.f[a.f_shared ? p : so + p] / diag_at(g, l2, gi, gj, p);
-            } else if (PRO == PRO_PROLONG) {
-                v = src[p] + prolong_at(a.ec + (size_t)slot * (n >> 2), gi, gj,
-                                        nv, nh, per);
-            } else {   // PRO_PROLONG_JAC
-                v = cj * a.f[a.f_shared ? p : so + p] / diag_at(g, l2, gi, gj, p) +
-                    prolong_at(a.ec + (size_t)slot * (n >> 2), gi, gj, nv, nh, per);
+    {
+        const int pad = T.SX - T.CX;
+        for (int e = t; e < T.RY * pad; e += NT) {
+            const int ii = e / pad;
+            vin[ii * T.SX + T.CX + (e - ii * pad)] = 0.0;
+        }
+    }
+    {
+        const int pad = T.SH - T.NHR;
+        for (int e = t; e < T.CO * pad; e += NT) {
+            const int c = e / pad, q = T.NHR + (e - c * pad);
+            ht[c * T.SH + q] = 0.0;
+        }
+    }
+    __syncthreads();
+
+    // 2. horizontal pass of G_h over the rows the vertical pass needs:
+    //    ht(q, c) = sum_k G_h(c, k) v(q + hv - lo - bwv, c - lo + hh - bwh + k)
+    for (int e = t; e < T.NHR * T.NWH; e += NT) {
+        const int w = e / T.NHR, q = e - w * T.NHR;       // lanes along rows
+        const int c0 = w * HWIN;
+        const double* rowp = vin + (q + T.hv - T.lo - T.bwv) * T.SX +
+                             (c0 - T.lo + T.hh - T.bwh);
+        double acc[HWIN];
+#pragma unroll
+        for (int o = 0; o < HWIN; ++o) acc[o] = 0.0;
+        if (g.gh.uniform) {
+            for (int k0 = 0; k0 < T.WHP; k0 += CH) {
+                double win[HWIN + CH - 1];
+#pragma unroll
+                for (int m = 0; m < HWIN + CH - 1; ++m)
+                    win[m] = rowp[k0 + m];
+#pragma unroll
+                for (int k = 0; k < CH; ++k) {
+                    const double tp = ch[k0 + k];
+#pragma unroll
+                    for (int o = 0; o < HWIN; ++o) acc[o] += tp * win[o + k];
+                }
+            }
+        } else {
+            // per-column coefficients: rotating window, one tap at a time
+            double win[HWIN];
+#pragma unroll
+            for (int m = 0; m < HWIN; ++m) win[m] = rowp[m];
+            const double* cf = ch + c0 * T.WHP;
+            for (int k = 0; k < T.WH; ++k) {
+#pragma unroll
+                for (int o = 0; o < HWIN; ++o) acc[o] += cf[o * T.WHP + k] * win[o];
+#pragma unroll
+                for (int o = 0; o < HWIN - 1; ++o) win[o] = win[o + 1];
+                win[HWIN - 1] = rowp[k + HWIN];
             }
         }
-        vin[jj * T.SY + ii] = v;
+#pragma unroll
+        for (int o = 0; o < HWIN; ++o)
+            if (c0 + o < T.CO) ht[(c0 + o) * T.SH + q] = acc[o];
     }
     __syncthreads();
 
-    // 2. vertical pass over output rows [-lo, TILE_Y) of every loaded column
-    if (g.gv.uniform) {
-        vert_window(vin, vt, cv, T, bwv, i0, nv, per);
-    } else
-    for (int e = threadIdx.x; e < T.RO * T.CX; e += APPLY_THREADS) {
-        const int jj = e / T.RO, r = e - jj * T.RO;        // r = row + lo
-        const int gi = i0 + r - T.lo;
-        double s = 0.0;
-        if (gi < nv && (gi >= 0 || per)) {
-            const double* col = vin + jj * T.SY + r - T.lo + T.hv - bwv;
-            const double* cf = cv + r * T.WVP;
-#pragma unroll 4
-            for (int k = 0; k < T.WV; ++k) s += cf[k] * col[k];
+    // 3. vertical pass of G_v: (G v)(r, c) = sum_k G_v(r, k) ht(r + k, c)
+    double vacc[VWIN];
+    const int vw = t / T.CO, vcol = t - vw * T.CO;        // lanes along columns
+    const bool vown = t < T.CO * T.NWV;
+    if (vown) {
+        const int r0 = vw * VWIN;
+        const double* colp = ht + vcol * T.SH + r0;
+#pragma unroll
+        for (int o = 0; o < VWIN; ++o) vacc[o] = 0.0;
+        if (g.gv.uniform) {
+            for (int k0 = 0; k0 < T.WVP; k0 += CH) {
+                double win[VWIN + CH - 1];
+#pragma unroll
+                for (int m = 0; m < VWIN + CH - 1; ++m) win[m] = colp[k0 + m];
+#pragma unroll
+                for (int k = 0; k < CH; ++k) {
+                    const double tp = cv[k0 + k];
+#pragma unroll
+                    for (int o = 0; o < VWIN; ++o) vacc[o] += tp * win[o + k];
+                }
+            }
+        } else {
+            double win[VWIN];
+#pragma unroll
+            for (int m = 0; m < VWIN; ++m) win[m] = colp[m];
+            const double* cf = cv + r0 * T.WVP;
+            for (int k = 0; k < T.WV; ++k) {
+#pragma unroll
+                for (int o = 0; o < VWIN; ++o) vacc[o] += cf[o * T.WVP + k] * win[o];
+#pragma unroll
+                for (int o = 0; o < VWIN - 1; ++o) win[o] = win[o + 1];
+                win[VWIN - 1] = colp[k + VWIN];
+            }
         }
-        vt[jj * T.SO + r] = s;
+    }
+    __syncthreads();
+    if (vown) {
+#pragma unroll
+        for (int o = 0; o < VWIN; ++o) {
+            const int r = vw * VWIN + o;
+            if (r < T.RO) kvs[vcol * T.SR + r] = vacc[o];
+        }
     }
     __syncthreads();
 
-    // 3.-5. horizontal pass, stencil, epilogue
+    // 4. stencil term and epilogue (lanes along the contiguous axis)
     double dot = 0.0;
-    for (int e = threadIdx.x; e < nout; e += APPLY_THREADS) {
-        const int c = e / T.RO, r = e - c * T.RO;          // local + lo
+    const int nout = T.RO * T.CO;
+#pragma unroll
+    for (int k = 0; k < NPRE; ++k)
+        out_point<PRO, EPI>(pre[k], t + k * NT, a, sp, T, vin, kvs, l2, dgl, c0,
+                            c1, i0, j0, dot);
+    for (int e = t + NPRE * NT; e < nout; e += NT) {
         OutPre q;
-        if (e == (int)threadIdx.x) q = pre;
-        else out_load<PRO, EPI>(q, e, a, T, i0, j0, so, l2);
-        if (!q.ok) {
-            if (EXT) rs[c * T.SR + r] = 0.0;
-            continue;
-        }
-        double kv = 0.0;
-        {
-            const double* row = vt + (c - T.lo + T.hh - bwh) * T.SO + r;
-            const double* cf = ch + (g.gh.uniform ? 0 : c) * T.WH;
-#pragma unroll 4
-            for (int k = 0; k < T.WH; ++k) kv += cf[k] * row[k * T.SO];
-        }
-        const double* vc = vin + (c - T.lo + T.hh) * T.SY + r - T.lo + T.hv;
-        double sv = q.sc * vc[0];
-        sv += q.sn * vc[1];
-        sv += q.snm * vc[-1];
-        sv += q.se * vc[T.SY];
-        sv += q.sem * vc[-T.SY];
-        if (g.S.nine) {
-            sv += q.sne * vc[T.SY + 1];
-            sv += q.snem * vc[-T.SY - 1];
-            sv += q.sse * vc[T.SY - 1];
-            sv += q.ssep * vc[-T.SY + 1];
-        }
-        kv += l2 * sv;
-        const double v = vc[0];
-        const size_t o = so + q.gi + (int64_t)nv * q.gj;
-        if (EPI == EPI_STORE) {
-            a.out[o] = kv;
-        } else if (EPI == EPI_DOT) {
-            a.out[o] = kv;
-            dot += v * kv;
-        } else if (EPI == EPI_RESID) {
-            a.out[o] = q.f - kv;
-        } else if (EPI == EPI_RESTRICT) {
-            rs[c * T.SR + r] = q.f - kv;
-        } else {   // EPI_CHEB
-            const double* cc = a.cheb + (size_t)slot * a.cheb_stride;
-            const double dprev = PRO == PRO_JACOBI ? v : q.d;
-            const double dn = cc[0] * dprev + cc[1] * (q.f - kv) / q.dg;
-            a.d[o] = dn;
-            const double xn = v + dn;
-            a.out[o] = xn;
-            if (a.dot) dot += q.f * xn;
-        }
+        out_load<PRO, EPI>(q, e, a, sp, T, i0, j0);
+        out_point<PRO, EPI>(q, e, a, sp, T, vin, kvs, l2, dgl, c0, c1, i0, j0,
+                            dot);
     }
+
     if (EPI == EPI_RESTRICT) {
         // full weighting of the residual tile onto the coarse points whose
         // centre lies in the tile: fc(I, J) = sum P(f, (I, J)) res(f)
         __syncthreads();
+        const double* rs = kvs;
         const int nvc = nv >> 1, nhc = nh >> 1;
         const int I0 = i0 >> 1, J0 = j0 >> 1;
         constexpr int CI = TILE_Y / 2, CJ = TILE_X / 2;
-        for (int e = threadIdx.x; e < CI * CJ; e += APPLY_THREADS) {
+        for (int e = t; e < CI * CJ; e += NT) {
             const int cjj = e / CI, cii = e - cjj * CI;
             const int I = I0 + cii, J = J0 + cjj;
             if (I >= nvc || J >= nhc) continue;
@@ -385,14 +584,22 @@ __device__ __forceinline__ void apply_body(const ApplyArgs& a, double* lds,
         }
     }
     if (EPI == EPI_DOT || (EPI == EPI_CHEB && a.dot)) {
-        const double s = block_sum<APPLY_THREADS>(dot, red);
-        if (threadIdx.x == 0)
-            a.part[(size_t)slot * a.part_stride + tile] = s;
+        const double s = block_sum<NT>(dot, red);
+        if (t == 0) a.part[(size_t)slot * a.part_stride + tile] = s;
     }
 }
 
+// Register budget: RLS_APPLY_WAVES waves per SIMD, i.e. that many
+// 256-thread workgroups per CU (2: at most 256 VGPRs).
+#ifndef RLS_APPLY_WAVES
+#define RLS_APPLY_WAVES 2
+#endif
+#define RLS_APPLY_BOUNDS           \
+    __launch_bounds__(APPLY_THREADS) \
+    __attribute__((amdgpu_waves_per_eu(RLS_APPLY_WAVES)))
+
 template <int PRO, int EPI>
-__global__ void __launch_bounds__(APPLY_THREADS) k_apply(ApplyArgs a) {
+__global__ void RLS_APPLY_BOUNDS k_apply(ApplyArgs a) {
     extern __shared__ double lds[];
     __shared__ double red[APPLY_THREADS];
     apply_body<PRO, EPI>(a, lds, red);
@@ -401,7 +608,7 @@ __global__ void __launch_bounds__(APPLY_THREADS) k_apply(ApplyArgs a) {
 // The finest-level Chebyshev step (plain prologue) under a name of its own,
 // so that profiles separate the sweep's most frequent kernel from the same
 // step on coarser levels.
-__global__ void __launch_bounds__(APPLY_THREADS) k_smooth_fine(ApplyArgs a) {
+__global__ void RLS_APPLY_BOUNDS k_smooth_fine(ApplyArgs a) {
     extern __shared__ double lds[];
     __shared__ double red[APPLY_THREADS];
     apply_body<PRO_PLAIN, EPI_CHEB>(a, lds, red);
@@ -425,8 +632,7 @@ static void launch_one(const ApplyArgs& a, hipStream_t s) {
     dim3 grid((a.g.nv + TILE_Y - 1) / TILE_Y, (a.g.nh + TILE_X - 1) / TILE_X,
               a.nslot);
     hipLaunchKernelGGL((k_apply<PRO, EPI>), grid, dim3(APPLY_THREADS),
-                       sizeof(double) * T.lds_doubles(EPI == EPI_RESTRICT), s,
-                       a);
+                       sizeof(double) * T.lds_doubles(), s, a);
 }
 
 // Every (prologue, epilogue) pair in use.
@@ -467,7 +673,7 @@ int apply_tiles(const LevelGeom& g) {
 
 size_t apply_lds_bytes(const LevelGeom& g, int epi) {
     const TileShape T(g, epi == EPI_RESTRICT);
-    return sizeof(double) * T.lds_doubles(epi == EPI_RESTRICT);
+    return sizeof(double) * T.lds_doubles();
 }
 
 void launch_smooth_fine(const ApplyArgs& a, hipStream_t s) {
@@ -475,7 +681,7 @@ void launch_smooth_fine(const ApplyArgs& a, hipStream_t s) {
     dim3 grid((a.g.nv + TILE_Y - 1) / TILE_Y, (a.g.nh + TILE_X - 1) / TILE_X,
               a.nslot);
     hipLaunchKernelGGL(k_smooth_fine, grid, dim3(APPLY_THREADS),
-                       sizeof(double) * T.lds_doubles(0), s, a);
+                       sizeof(double) * T.lds_doubles(), s, a);
 }
 
 void launch_apply(int pro, int epi, const ApplyArgs& a, hipStream_t s) {

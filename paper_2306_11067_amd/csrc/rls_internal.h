@@ -51,7 +51,7 @@ struct LevelGeom {
 // Tile of the level-operator kernel (i is the contiguous axis).
 constexpr int TILE_Y = 64;
 constexpr int TILE_X = 16;
-constexpr int APPLY_THREADS = 1024;
+constexpr int APPLY_THREADS = 256;
 
 // Prologue: how the operand v of K v is formed while loading a tile.
 enum Prologue : int {

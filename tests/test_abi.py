@@ -88,3 +88,19 @@ def test_unsupported_boundary_pair_without_gpu():
     h = C.c_void_p()
     assert lib.rls_setup(C.byref(h), C.byref(op), C.byref(g), None,
                          None) == L.RLS_E_UNSUPPORTED
+
+
+def test_blur_radius_beyond_lds_tile_rejected_without_gpu():
+    lib = L.load()
+    r = 40
+    taps = (C.c_double * (2 * r + 1))(*([1.0 / (2 * r + 1)] * (2 * r + 1)))
+    op = L.OpDesc()
+    op.kind = L.RLS_OP_BLUR_SEPARABLE
+    op.bc = L.RLS_BC_REFLECTIVE
+    op.r_v = op.r_h = r
+    op.taps_v = op.taps_h = C.cast(taps, C.POINTER(C.c_double))
+    g = L.GridDesc(512, 512, L.RLS_L_NEUMANN, 5, 2, 4.0, L.RLS_PREC_FP64, 0, 0.0)
+    h = C.c_void_p()
+    assert lib.rls_setup(C.byref(h), C.byref(op), C.byref(g), None,
+                         None) == L.RLS_E_UNSUPPORTED
+    assert b"LDS" in lib.rls_last_error()
