@@ -150,6 +150,10 @@ struct rls_problem {
     int unit_weights = 1;
     Work w;
     hipStream_t cstream = nullptr;   // capture stream for iteration graphs
+    // Host copy of the device slot list w.slots while a sweep launches
+    // iterations over it (copied into the kernel arguments when short).
+    const int* hslots = nullptr;
+    int hslots_n = 0;
     // live timing of the finest-level Chebyshev-step kernel
     bool timer_on = false;
     struct TimedRun {
@@ -474,6 +478,17 @@ struct CycleCtl {
     int dot_stride = 0;
 };
 
+// Put the slot list in the kernel arguments when it is the sweep's list
+// and short enough.
+static void inline_slots(const rls_problem* P, ApplyArgs& a) {
+    a.zn = 0;
+    if (!a.slots || a.slots != P->w.slots.as<int>() || !P->hslots ||
+        P->hslots_n != a.nslot || a.nslot > ZINLINE)
+        return;
+    for (int i = 0; i < a.nslot; ++i) a.zslot[i] = P->hslots[i];
+    a.zn = a.nslot;
+}
+
 // z = V-cycle(f) on level k (Algorithm 1, gamma = 1, V(nu, nu)), for the
 // nslot slots listed in `slots` (null: slots 0..nslot-1).
 void vcycle(rls_problem* P, int k, int nslot, const int* slots,
@@ -531,6 +546,7 @@ void vcycle(rls_problem* P, int k, int nslot, const int* slots,
     a.d = d;
     a.cheb_stride = cs;
     a.cheb_first = cheb;
+    inline_slots(P, a);
     auto gate_first = [&](ApplyArgs& aa) {
         if (top && ctl.gate) {
             aa.gate = 1;
@@ -957,6 +973,7 @@ rls_status rls_solve_sweep(rls_problem* p, const double* b, const double* lam,
         ak.g = g0;
         ak.nslot = nact;
         ak.slots = sl;
+        inline_slots(p, ak);
         ak.lam2 = w.lam2.as<double>();
         ak.active = active;
         ak.in = z;
@@ -1006,6 +1023,8 @@ rls_status rls_solve_sweep(rls_problem* p, const double* b, const double* lam,
         if (nact == 0) break;
         RLS_HIP(hipMemcpyAsync(w.slots.p, hsl, sizeof(int) * nact,
                                hipMemcpyHostToDevice, s));
+        p->hslots = hsl;        // slots only ever leave the active set, so a
+        p->hslots_n = nact;     // captured chunk's list is fixed by nact
         if (!o.graph || p->timer_on) {
             for (int k = 0; k < chunk; ++k) iteration(nact, k & 1, s);
             status = check_launch("pcg iteration");
@@ -1039,6 +1058,8 @@ rls_status rls_solve_sweep(rls_problem* p, const double* b, const double* lam,
         }
     }
     if (exec) hipGraphExecDestroy(exec);
+    p->hslots = nullptr;
+    p->hslots_n = 0;
     if (status != RLS_OK) return status;
 
     // true residual ||f - K x||, L-curve pair (||A x - b||, ||D L x||)

@@ -264,7 +264,8 @@ __device__ __forceinline__ void apply_body(const ApplyArgs& a, double* lds,
     constexpr int EXT = EPI == EPI_RESTRICT ? 1 : 0;
     constexpr int NT = APPLY_THREADS;
     const int t = threadIdx.x;
-    const int slot = a.slots ? a.slots[blockIdx.z] : (int)blockIdx.z;
+    const int z = blockIdx.z;
+    const int slot = z < a.zn ? a.zslot[z] : a.slots ? a.slots[z] : z;
     // A slot that stopped inside a replayed chunk is skipped.  Variants
     // without folded PCG scalars only test the flag once their loads are
     // in flight (reading a stopped slot is harmless, writing is not).

@@ -86,10 +86,16 @@ struct SlotState {
     int maxit;
 };
 
+// Slot lists up to this length also travel in the kernel arguments (read
+// through the scalar kernel-argument path instead of a global load).
+constexpr int ZINLINE = 32;
+
 struct ApplyArgs {
     LevelGeom g;
     int nslot = 0;                   // grid z: number of slots launched
     const int* slots = nullptr;      // slot of each grid z (null: identity)
+    int zn = 0;                      // zn == nslot: zslot holds the list
+    int zslot[ZINLINE] = {};
     const double* lam2 = nullptr;    // per slot lambda^2
     const int* active = nullptr;     // per slot, may be null (all active)
     const double* in = nullptr;      // v, z (PUPDATE) or x (PROLONG)

@@ -2,7 +2,8 @@
 
 The 512 x 512 deblurring workload (3 outer weightings x 20 lambdas in
 [1e-5, 1]) is solved on the GPU exactly as bench.py does (same smoothing
-settings, relative residual 1e-12, graph-replayed iteration chunks) and
+settings, relative residual 1e-12, graph-replayed iteration chunks, each
+weighting's sweep warm-started from the previous one's solutions) and
 every one of the 60 solutions is compared with the oracle's x*(lambda)
 computed to the FP64 floor (DCT closed form for D = I, CG preconditioned by
 the exact D = I inverse otherwise).  Bar: relative error <= 1e-6 in x and
@@ -20,23 +21,35 @@ pytestmark = pytest.mark.gpu
 
 
 @pytest.fixture(scope="module")
-def setup():
+def sweeps():
+    import torch
     from paper_2306_11067_amd import Problem
     P_ = W.config2()
     prob = Problem(P_.nv, P_.nh, P_.taps_v, P_.taps_h, P_.bc, P_.lbc,
                    P_.levels, nu=bench.NU_FINE, cheb_ratio=bench.RATIO_FINE,
                    weights=dev(P_.weights[0]), nu_coarse=bench.NU_COARSE,
                    cheb_ratio_coarse=bench.RATIO_COARSE)
-    return P_, prob, dev(P_.b)
+    b = dev(P_.b)
+    D = [dev(w) for w in P_.weights]
+    n = P_.nv * P_.nh
+    bufs = [torch.empty(len(P_.lams) * n, dtype=torch.float64,
+                        device=b.device) for _ in range(2)]
+    out = []
+    x0 = None
+    for ell, d in enumerate(D):
+        prob.set_weights(d)
+        x, res, sem, info = prob.solve_sweep(b, P_.lams, bench.TOL, x0=x0,
+                                             x=bufs[ell & 1], maxit=400000,
+                                             poll_every=16)
+        out.append((host(x).copy(), res, sem, info))
+        x0 = x
+    return P_, out
 
 
 @pytest.mark.parametrize("ell", [0, 1, 2])
-def test_bench_workload_matches_oracle(setup, ell):
-    P_, prob, b = setup
-    prob.set_weights(dev(P_.weights[ell]))
-    x, res, sem, info = prob.solve_sweep(b, P_.lams, bench.TOL, maxit=400000,
-                                         poll_every=16)
-    x = host(x)
+def test_bench_workload_matches_oracle(sweeps, ell):
+    P_, out = sweeps
+    x, res, sem, info = out[ell]
     O = DeblurOracle(P_.nv, P_.nh, P_.taps_v, P_.taps_h, P_.bc, P_.lbc,
                      P_.weights[ell], P_.levels)
     worst = 0.0
