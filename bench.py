@@ -15,8 +15,11 @@ previous weighting's solutions (warm start across outer iterations).
 Prints one JSON line.  `value` = solves / second of the timed steps with the
 inputs resident in HBM.  `roofline` reports the most frequent kernel (the
 finest-level Chebyshev smoothing step) from HIP events around every run of
-its consecutive launches in a second pass over the same step.  `cpu_baseline` times the CPU
-oracle on a bounded sample (see its `sample` field).
+its consecutive launches in a second pass over the same step.  `mixed_fp32`
+times the same step once more with the V-cycle in FP32 under flexible FP64
+PCG (same tolerance; its solutions meet the same 1e-6 bar in the GPU test
+suite) and reports its speedup over the FP64 step.  `cpu_baseline` times
+the CPU oracle on a bounded sample (see its `sample` field).
 """
 from __future__ import annotations
 
@@ -116,6 +119,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-roofline", action="store_true")
+    ap.add_argument("--no-mixed", action="store_true")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (got --gpus {args.gpus}); the "
@@ -176,6 +180,33 @@ def main():
         print(f"roofline pass: {launches} launches, {1e6 * avg_s:.2f} us "
               f"avg, {achieved:.1f} GB/s", file=sys.stderr, flush=True)
 
+    mixed = None
+    if not args.no_mixed:
+        # the same step with the FP32 V-cycle under flexible FP64 PCG
+        prob32 = Problem(P_.nv, P_.nh, P_.taps_v, P_.taps_h, P_.bc, P_.lbc,
+                         P_.levels, nu=NU_FINE, cheb_ratio=RATIO_FINE,
+                         weights=D[0], nu_coarse=NU_COARSE,
+                         cheb_ratio_coarse=RATIO_COARSE,
+                         precision="mixed_fp32")
+        prob32.solve_sweep(b, lams, TOL, maxit=2, poll_every=2)
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        inf32 = run_step(prob32, b, D, lams, bufs)
+        torch.cuda.synchronize()
+        el32 = time.perf_counter() - t1
+        conv32 = all(i["flags"] & 1 for info in inf32 for i in info)
+        it32 = [i["iters"] for info in inf32 for i in info]
+        prob32.close()
+        mixed = {"value": len(lams) * len(D) / el32, "unit": "solves/s",
+                 "ms_per_step": 1e3 * el32,
+                 "speedup_vs_fp64": (elapsed / args.steps) / el32,
+                 "all_converged": conv32, "max_iterations": max(it32),
+                 "arithmetic": "FP32 V-cycle (vectors, bands, stencils), "
+                               "FP64 PCG vectors, dots, residual, tail"}
+        print(f"mixed step in {el32:.2f} s (speedup "
+              f"{mixed['speedup_vs_fp64']:.2f}), all converged: {conv32}, "
+              f"max iterations {max(it32)}", file=sys.stderr, flush=True)
+
     cpu = None
     if not args.no_cpu_baseline:
         cpu = cpu_baseline(P_, iters)
@@ -197,6 +228,7 @@ def main():
         "config": workload_config(P_),
         "roofline": roof,
         "cpu_baseline": cpu,
+        "mixed_fp32": mixed,
     }
     print(json.dumps(out), flush=True)
 

@@ -72,8 +72,17 @@ typedef int rls_status;
 #define RLS_L_NEUMANN  0
 #define RLS_L_PERIODIC 1
 
-/* Arithmetic of the iteration. */
-#define RLS_PREC_FP64 0
+/* Arithmetic of the iteration.  FP64: everything in double precision.
+ * MIXED_FP32: the PCG iteration (x, r, p, q, all dot products, the
+ * convergence test and the final residual) stays FP64; the V-cycle
+ * preconditioner (level vectors, Gram bands, Galerkin stencils and their
+ * arithmetic) runs in FP32, except the coarse tail levels and the coarsest
+ * Cholesky solve, which stay FP64.  An FP32 V-cycle is not exactly the same
+ * linear map at every application, so PCG then uses the flexible
+ * (Polak-Ribiere) beta; the attainable accuracy is that of the FP64
+ * residual (Sec. 3, Algorithm 1 as the preconditioner of CG). */
+#define RLS_PREC_FP64       0
+#define RLS_PREC_MIXED_FP32 1
 
 /* Tolerance semantics of rls_solve_sweep. */
 #define RLS_TOL_RELATIVE 0   /* ||A^T b - K x_i|| <= tol * ||A^T b||      */
@@ -112,7 +121,7 @@ typedef struct {
     double cheb_ratio;      /* finest-level smoothing interval
                                [rho/ratio, rho], rho the Gershgorin bound of
                                diag(K_k)^-1 K_k; > 1                         */
-    int precision;          /* RLS_PREC_FP64                                 */
+    int precision;          /* RLS_PREC_FP64 or RLS_PREC_MIXED_FP32          */
     int nu_coarse;          /* same on the coarser levels (0: = nu), 1..64  */
     double cheb_ratio_coarse; /* same on the coarser levels (0: = cheb_ratio) */
 } rls_grid_desc;

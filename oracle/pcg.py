@@ -15,11 +15,16 @@ from .multigrid import Hierarchy, SparseOp, VCycle
 
 
 def pcg(K, f, M=None, x0=None, tol=1e-8, maxit=10000, absolute=False,
-        stall=None):
+        stall=None, flexible=False):
     """Solve K x = f.  Returns (x, iterations, final recursive ||r||, history).
 
     stall: stop when the best residual has not decreased for this many steps
     (used to iterate to the floating-point floor).
+    flexible: Polak-Ribiere beta = z_new . (r_new - r_old) / (r_old . z_old)
+    (flexible CG, Notay 2000), for a preconditioner that is not the same
+    linear map at every application (e.g. a V-cycle evaluated in reduced
+    precision); with a fixed SPD M it gives the same iterates as the
+    standard beta.
     """
     x = np.zeros_like(f) if x0 is None else np.array(x0, dtype=np.float64)
     r = f - K(x) if x0 is not None else f.copy()
@@ -35,6 +40,7 @@ def pcg(K, f, M=None, x0=None, tol=1e-8, maxit=10000, absolute=False,
         q = K(p)
         alpha = gamma / float(p @ q)
         x += alpha * p
+        r_old = r.copy() if flexible else None
         r -= alpha * q
         nr = float(np.linalg.norm(r))
         hist.append(nr)
@@ -49,7 +55,11 @@ def pcg(K, f, M=None, x0=None, tol=1e-8, maxit=10000, absolute=False,
                     return x, it, nr, hist
         z = r.copy() if M is None else M(r)
         gnew = float(r @ z)
-        p = z + (gnew / gamma) * p
+        if flexible:
+            beta = float(z @ (r - r_old)) / gamma
+        else:
+            beta = gnew / gamma
+        p = z + beta * p
         gamma = gnew
     return x, maxit, hist[-1], hist
 

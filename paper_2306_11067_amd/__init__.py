@@ -19,6 +19,7 @@ __all__ = ["Problem", "RLSError", "BC", "LBC"]
 BC = {"periodic": L.RLS_BC_PERIODIC, "reflective": L.RLS_BC_REFLECTIVE,
       "zero": L.RLS_BC_ZERO}
 LBC = {"neumann": L.RLS_L_NEUMANN, "periodic": L.RLS_L_PERIODIC}
+PREC = {"fp64": L.RLS_PREC_FP64, "mixed_fp32": L.RLS_PREC_MIXED_FP32}
 
 
 class RLSError(RuntimeError):
@@ -58,7 +59,7 @@ class Problem:
 
     def __init__(self, nv, nh, taps_v, taps_h, bc="reflective", lbc="neumann",
                  levels=3, nu=2, cheb_ratio=4.0, weights=None, nu_coarse=0,
-                 cheb_ratio_coarse=0.0):
+                 cheb_ratio_coarse=0.0, precision="fp64"):
         self._lib = L.load()
         self.nv, self.nh, self.levels = int(nv), int(nh), int(levels)
         self.n = self.nv * self.nh
@@ -71,7 +72,7 @@ class Problem:
         op.r_h = (len(th) - 1) // 2
         op.taps_v, op.taps_h = ptv, pth
         g = L.GridDesc(self.nv, self.nh, LBC[lbc], self.levels, int(nu),
-                       float(cheb_ratio), L.RLS_PREC_FP64, int(nu_coarse),
+                       float(cheb_ratio), PREC[precision], int(nu_coarse),
                        float(cheb_ratio_coarse))
         h = C.c_void_p()
         d = None if weights is None else _dptr(weights, "weights", 2 * self.n)

@@ -7,6 +7,7 @@
 #include <cstring>
 #include <memory>
 #include <string>
+#include <type_traits>
 #include <vector>
 
 #include "rls_internal.h"
@@ -73,8 +74,9 @@ rls_status dalloc(DBuf& b, size_t bytes) {
 
 struct Band {
     int n = 0, bw = 0, map = MAP_ZERO, uniform = 0;
-    size_t taps_off = 0;     // offset (in doubles) of the uniform row in table
+    size_t taps_off = 0;     // offset (in values) of the uniform row in table
     DBuf table, diag, rowabs;
+    DBuf table32, diag32;    // FP32 copies (FP32 V-cycle)
     BandDev dev() const {
         BandDev b;
         b.n = n;
@@ -87,6 +89,17 @@ struct Band {
         b.rowabs = rowabs.as<double>();
         return b;
     }
+    BandDevT<float> dev32() const {
+        BandDevT<float> b;
+        b.n = n;
+        b.bw = bw;
+        b.map = map;
+        b.uniform = uniform;
+        b.table = table32.as<float>();
+        b.taps = table32.as<float>() + taps_off;
+        b.diag = diag32.as<float>();
+        return b;
+    }
 };
 
 struct Level {
@@ -96,6 +109,7 @@ struct Level {
     int nine = 0;
     int periodic = 0;
     int64_t n() const { return (int64_t)nv * nh; }
+    DBuf planes32;           // FP32 copy of the five stencil planes
     LevelGeom geom() const {
         LevelGeom g;
         g.nv = nv;
@@ -114,7 +128,27 @@ struct Level {
         g.S.periodic = periodic;
         return g;
     }
+    LevelGeomT<float> geom32() const {
+        LevelGeomT<float> g;
+        g.nv = nv;
+        g.nh = nh;
+        g.gv = gv.dev32();
+        g.gh = gh.dev32();
+        const float* pl = planes32.as<float>();
+        const int64_t m = n();
+        g.S.c = pl;
+        g.S.cn = pl + m;
+        g.S.ce = pl + 2 * m;
+        g.S.cne = pl + 3 * m;
+        g.S.cse = pl + 4 * m;
+        g.S.nine = nine;
+        g.S.periodic = periodic;
+        return g;
+    }
+    template <class R> LevelGeomT<R> geom_t() const;
 };
+template <> LevelGeomT<double> Level::geom_t<double>() const { return geom(); }
+template <> LevelGeomT<float> Level::geom_t<float>() const { return geom32(); }
 
 // Per-sweep workspace, grown on demand.
 struct Work {
@@ -123,6 +157,9 @@ struct Work {
     DBuf f;                      // A^T b (n)
     DBuf fpart, rrpart, outv, slots;
     DBuf part_pq, part_rr, part_rz;    // PCG partial sums per slot
+    DBuf part_zq;                      // flexible beta: partials of z . q
+    DBuf r32, z32;                     // FP32 V-cycle: fine rhs and result
+    std::vector<DBuf> lx32, lxb32, ld32, lf32;   // FP32 level vectors
     int* h_active = nullptr;     // pinned host mirrors
     int* h_slots = nullptr;
     ~Work() {
@@ -138,6 +175,7 @@ struct Work {
 struct rls_problem {
     int device = 0;
     int nv = 0, nh = 0, levels = 0, bc = 0, lbc = 0;
+    int prec = RLS_PREC_FP64;    // V-cycle arithmetic
     std::vector<int> nu;         // Chebyshev steps per level
     std::vector<double> ratio;   // Chebyshev interval ratio per level
     int nu_max = 2;
@@ -212,6 +250,10 @@ void smooth_fine(rls_problem* P, const ApplyArgs& a, hipStream_t s) {
     launch_smooth_fine(a, s);
     if (P->timer_on) P->run_cur.launches += 1;
 }
+// FP32 V-cycle: not timed (the kernel timer covers the FP64 step).
+void smooth_fine(rls_problem*, const ApplyArgsT<float>& a, hipStream_t s) {
+    launch_smooth_fine(a, s);
+}
 
 void run_end(rls_problem* P, hipStream_t s) {
     if (!P->timer_on) return;
@@ -262,6 +304,7 @@ rls_status ensure_work(rls_problem* P, int nslot) {
         const int t0 = apply_tiles(P->lev[0].geom());
         RLS_TRY(dalloc(w.part_pq, sizeof(double) * (size_t)cap * t0));
         RLS_TRY(dalloc(w.part_rz, sizeof(double) * (size_t)cap * t0));
+        RLS_TRY(dalloc(w.part_zq, sizeof(double) * (size_t)cap * t0));
         RLS_TRY(dalloc(w.part_rr, sizeof(double) * (size_t)cap * vec_blocks(n)));
     }
     if (w.h_active) hipHostFree(w.h_active);
@@ -284,6 +327,20 @@ rls_status ensure_work(rls_problem* P, int nslot) {
         if (k > 0) {
             RLS_TRY(dalloc(w.lx[k], bytes));
             RLS_TRY(dalloc(w.lf[k], bytes));
+        }
+    }
+    if (P->prec == RLS_PREC_MIXED_FP32) {
+        RLS_TRY(dalloc(w.r32, sizeof(float) * (size_t)cap * n));
+        RLS_TRY(dalloc(w.z32, sizeof(float) * (size_t)cap * n));
+        for (auto* v : {&w.lx32, &w.lxb32, &w.ld32, &w.lf32}) v->resize(L);
+        for (int k = 0; k < L; ++k) {
+            const size_t bytes = sizeof(float) * (size_t)cap * P->lev[k].n();
+            RLS_TRY(dalloc(w.lxb32[k], bytes));
+            RLS_TRY(dalloc(w.ld32[k], bytes));
+            if (k > 0) {
+                RLS_TRY(dalloc(w.lx32[k], bytes));
+                RLS_TRY(dalloc(w.lf32[k], bytes));
+            }
         }
     }
     w.cap = cap;
@@ -364,6 +421,15 @@ rls_status build_direction(rls_problem* P, const std::vector<double>& taps,
             G.uniform = 0;
             G.map = MAP_ZERO;
         }
+        if (P->prec == RLS_PREC_MIXED_FP32) {
+            const size_t tn = (size_t)nk * (2 * bw + 1);
+            RLS_TRY(dalloc(G.table32, sizeof(float) * tn));
+            RLS_TRY(dalloc(G.diag32, sizeof(float) * nk));
+            launch_to_f32(G.table.as<double>(), (int64_t)tn, 1, nullptr,
+                          G.table32.as<float>(), s);
+            launch_to_f32(G.diag.as<double>(), nk, 1, nullptr,
+                          G.diag32.as<float>(), s);
+        }
         bw = (bw + 2) / 2;
     }
     RLS_TRY(check_launch("build_direction"));
@@ -408,6 +474,11 @@ rls_status install_weights(rls_problem* P, const double* d, hipStream_t s) {
                                     P->periodic, L.planes.as<double>(), s);
         launch_stencil_rowabs(L.planes.as<double>(), L.nv, L.nh, P->periodic,
                               L.srowabs.as<double>(), s);
+        if (P->prec == RLS_PREC_MIXED_FP32) {
+            RLS_TRY(dalloc(L.planes32, sizeof(float) * 5 * m));
+            launch_to_f32(L.planes.as<double>(), 5 * m, 1, nullptr,
+                          L.planes32.as<float>(), s);
+        }
     }
     RLS_TRY(check_launch("install_weights"));
     return RLS_OK;
@@ -480,7 +551,8 @@ struct CycleCtl {
 
 // Put the slot list in the kernel arguments when it is the sweep's list
 // and short enough.
-static void inline_slots(const rls_problem* P, ApplyArgs& a) {
+template <class R>
+static void inline_slots(const rls_problem* P, ApplyArgsT<R>& a) {
     a.zn = 0;
     if (!a.slots || a.slots != P->w.slots.as<int>() || !P->hslots ||
         P->hslots_n != a.nslot || a.nslot > ZINLINE)
@@ -491,8 +563,22 @@ static void inline_slots(const rls_problem* P, ApplyArgs& a) {
 
 // z = V-cycle(f) on level k (Algorithm 1, gamma = 1, V(nu, nu)), for the
 // nslot slots listed in `slots` (null: slots 0..nslot-1).
+template <class R>
+R* lvec(std::vector<DBuf>& v64, std::vector<DBuf>& v32, int k);
+template <>
+double* lvec<double>(std::vector<DBuf>& v64, std::vector<DBuf>&, int k) {
+    return v64[k].as<double>();
+}
+template <>
+float* lvec<float>(std::vector<DBuf>&, std::vector<DBuf>& v32, int k) {
+    return v32[k].as<float>();
+}
+
+// R is the V-cycle's value type (double, or float under flexible PCG); the
+// coarse tail always computes in FP64.
+template <class R>
 void vcycle(rls_problem* P, int k, int nslot, const int* slots,
-            const int* active, const double* f, double* z, const CycleCtl& ctl,
+            const int* active, const R* f, R* z, const CycleCtl& ctl,
             hipStream_t s) {
     Work& w = P->w;
     const int L = P->levels;
@@ -500,7 +586,7 @@ void vcycle(rls_problem* P, int k, int nslot, const int* slots,
     const int nu = P->nu[k];
     const bool top = k == 0;
     if (k >= P->kt) {
-        TailArgs t;
+        TailArgsT<R> t;
         t.nlev = L - k;
         for (int i = 0; i < t.nlev; ++i) {
             const LevelGeom g = P->lev[k + i].geom();
@@ -533,10 +619,12 @@ void vcycle(rls_problem* P, int k, int nslot, const int* slots,
         launch_tail(t, nslot, s);
         return;
     }
-    const LevelGeom g = P->lev[k].geom();
+    // the kernel timer covers the FP64 finest-level step only
+    constexpr bool TIMED = std::is_same<R, double>::value;
+    const LevelGeomT<R> g = P->lev[k].template geom_t<R>();
     const double* cheb = w.cheb.as<double>() + (size_t)k * w.cap * cs;
-    double* d = w.ld[k].as<double>();
-    ApplyArgs a;
+    R* d = lvec<R>(w.ld, w.ld32, k);
+    ApplyArgsT<R> a;
     a.g = g;
     a.nslot = nslot;
     a.slots = slots;
@@ -547,7 +635,7 @@ void vcycle(rls_problem* P, int k, int nslot, const int* slots,
     a.cheb_stride = cs;
     a.cheb_first = cheb;
     inline_slots(P, a);
-    auto gate_first = [&](ApplyArgs& aa) {
+    auto gate_first = [&](ApplyArgsT<R>& aa) {
         if (top && ctl.gate) {
             aa.gate = 1;
             aa.st = ctl.st;
@@ -556,17 +644,17 @@ void vcycle(rls_problem* P, int k, int nslot, const int* slots,
             aa.nrr = ctl.nrr;
         }
     };
-    double* fc = w.lf[k + 1].as<double>();
-    double* zc = w.lx[k + 1].as<double>();
+    R* fc = lvec<R>(w.lf, w.lf32, k + 1);
+    R* zc = lvec<R>(w.lx, w.lx32, k + 1);
     if (nu == 1) {
         // x1 = c f / diag never leaves the tiles: the restriction kernel
         // forms it on the fly, the correction kernel forms it again.
-        ApplyArgs r = a;
+        ApplyArgsT<R> r = a;
         gate_first(r);
         r.fc = fc;
         launch_apply(PRO_JACOBI, EPI_RESTRICT, r, s);
-        vcycle(P, k + 1, nslot, slots, active, fc, zc, CycleCtl(), s);
-        ApplyArgs c = a;
+        vcycle(P, k + 1, nslot, slots, active, (const R*)fc, zc, CycleCtl(), s);
+        ApplyArgsT<R> c = a;
         c.ec = zc;
         c.out = z;
         c.cheb = cheb;
@@ -582,20 +670,20 @@ void vcycle(rls_problem* P, int k, int nslot, const int* slots,
     // nu - 2 more pre steps and nu post steps each swap; choose buffer 0 so
     // that the result lands in z.
     const int swaps = (nu - 2) + nu;
-    double* bufs[2];
+    R* bufs[2];
     bufs[swaps % 2 == 0 ? 0 : 1] = z;
-    bufs[swaps % 2 == 0 ? 1 : 0] = w.lxb[k].as<double>();
+    bufs[swaps % 2 == 0 ? 1 : 0] = lvec<R>(w.lxb, w.lxb32, k);
     int cur = 0;
     {
-        ApplyArgs j = a;
+        ApplyArgsT<R> j = a;
         gate_first(j);
         j.out = bufs[cur];
         j.cheb = cheb + 2;
         launch_apply(PRO_JACOBI, EPI_CHEB, j, s);   // x1 = c f / diag, step 2
     }
-    if (top && nu > 2) run_begin(P, s);
+    if (TIMED && top && nu > 2) run_begin(P, s);
     for (int st = 2; st < nu; ++st) {
-        ApplyArgs c = a;
+        ApplyArgsT<R> c = a;
         c.in = bufs[cur];
         c.out = bufs[1 - cur];
         c.cheb = cheb + 2 * st;
@@ -603,16 +691,16 @@ void vcycle(rls_problem* P, int k, int nslot, const int* slots,
         else launch_apply(PRO_PLAIN, EPI_CHEB, c, s);
         cur = 1 - cur;
     }
-    if (top && nu > 2) run_end(P, s);
+    if (TIMED && top && nu > 2) run_end(P, s);
     {
-        ApplyArgs r = a;                            // residual + restriction
+        ApplyArgsT<R> r = a;                        // residual + restriction
         r.in = bufs[cur];
         r.fc = fc;
         launch_apply(PRO_PLAIN, EPI_RESTRICT, r, s);
     }
-    vcycle(P, k + 1, nslot, slots, active, fc, zc, CycleCtl(), s);
+    vcycle(P, k + 1, nslot, slots, active, (const R*)fc, zc, CycleCtl(), s);
     for (int st = 0; st < nu; ++st) {              // correction + smoothing
-        ApplyArgs c = a;
+        ApplyArgsT<R> c = a;
         c.in = bufs[cur];
         c.out = bufs[1 - cur];
         c.cheb = cheb + 2 * st;
@@ -622,10 +710,10 @@ void vcycle(rls_problem* P, int k, int nslot, const int* slots,
             c.part = ctl.dot_part;
             c.part_stride = ctl.dot_stride;
         }
-        if (top && st == 1) run_begin(P, s);
+        if (TIMED && top && st == 1) run_begin(P, s);
         if (top && st > 0) smooth_fine(P, c, s);
         else launch_apply(st == 0 ? PRO_PROLONG : PRO_PLAIN, EPI_CHEB, c, s);
-        if (top && st > 0 && st == nu - 1) run_end(P, s);
+        if (TIMED && top && st > 0 && st == nu - 1) run_end(P, s);
         cur = 1 - cur;
     }
 }
@@ -653,8 +741,9 @@ rls_status validate_grid(const rls_grid_desc* g) {
     const int64_t nc = (int64_t)(g->nv >> (g->levels - 1)) * (g->nh >> (g->levels - 1));
     if (nc > 1024)
         return fail(RLS_E_ARG, "coarsest level exceeds 1024 unknowns; add levels");
-    if (g->precision != RLS_PREC_FP64)
-        return fail(RLS_E_UNSUPPORTED, "only RLS_PREC_FP64 is supported");
+    if (g->precision != RLS_PREC_FP64 && g->precision != RLS_PREC_MIXED_FP32)
+        return fail(RLS_E_UNSUPPORTED,
+                    "precision must be RLS_PREC_FP64 or RLS_PREC_MIXED_FP32");
     return RLS_OK;
 }
 
@@ -712,6 +801,7 @@ rls_status rls_setup(rls_problem** out, const rls_op_desc* A,
     P->nv = g->nv;
     P->nh = g->nh;
     P->levels = g->levels;
+    P->prec = g->precision;
     for (int k = 0; k < g->levels; ++k) {
         const bool fine = k == 0;
         P->nu.push_back(fine || g->nu_coarse == 0 ? g->nu : g->nu_coarse);
@@ -836,7 +926,18 @@ rls_status rls_vcycle(rls_problem* p, const double* lam, int nlam,
     RLS_TRY(ensure_work(p, nlam));
     RLS_TRY(upload_lam(p, lam, nlam, s));
     RLS_TRY(prepare_sweep(p, nlam, s));
-    vcycle(p, 0, nlam, nullptr, nullptr, r, z, CycleCtl(), s);
+    if (p->prec == RLS_PREC_MIXED_FP32) {
+        Work& w = p->w;
+        const int64_t n = p->n();
+        launch_to_f32(r, n, nlam, nullptr, w.r32.as<float>(), s);
+        vcycle(p, 0, nlam, nullptr, nullptr, w.r32.as<float>(),
+               w.z32.as<float>(), CycleCtl(), s);
+        launch_vc_exit(nullptr, nullptr, nlam, n, apply_tiles(p->lev[0].geom()),
+                       w.z32.as<float>(), z, r, nullptr, w.part_rz.as<double>(),
+                       nullptr, s);
+    } else {
+        vcycle(p, 0, nlam, nullptr, nullptr, r, z, CycleCtl(), s);
+    }
     RLS_TRY(check_launch("rls_vcycle"));
     RLS_HIP(hipStreamSynchronize(s));
     return RLS_OK;
@@ -952,11 +1053,19 @@ rls_status rls_solve_sweep(rls_problem* p, const double* b, const double* lam,
     launch_sumsq_slots(r, n, ns, rrpart, s);
     // z0 = M r0 with partial sums of r0 . z0 (consumed by the first
     // iteration, where beta = 0 makes p0 = z0)
-    {
+    const bool mixed = p->prec == RLS_PREC_MIXED_FP32;
+    if (mixed) {
+        float* r32 = w.r32.as<float>();
+        float* z32 = w.z32.as<float>();
+        launch_to_f32(r, n, ns, nullptr, r32, s);
+        vcycle(p, 0, ns, nullptr, nullptr, (const float*)r32, z32, CycleCtl(), s);
+        launch_vc_exit(nullptr, nullptr, ns, n, tiles0, z32, z, r, nullptr,
+                       w.part_rz.as<double>(), nullptr, s);
+    } else {
         CycleCtl c0;
         c0.dot_part = w.part_rz.as<double>();
         c0.dot_stride = tiles0;
-        vcycle(p, 0, ns, nullptr, nullptr, r, z, c0, s);
+        vcycle(p, 0, ns, nullptr, nullptr, (const double*)r, z, c0, s);
     }
     launch_pcg_init(st, ns, fpart, vb, rrpart, vb, tol,
                     o.tol_mode == RLS_TOL_ABSOLUTE, o.maxit, active, s);
@@ -987,10 +1096,27 @@ rls_status rls_solve_sweep(rls_problem* p, const double* b, const double* lam,
         ak.part_rz = w.part_rz.as<double>();
         ak.nrz = tiles0;
         ak.parity = cur;
+        if (mixed) {
+            ak.flex = 1;
+            ak.part_zq = w.part_zq.as<double>();
+        }
         launch_apply(PRO_PUPDATE, EPI_DOT, ak, ss);
         launch_update_xr(st, active, sl, n, nact, x, r, pb[1 - cur], q,
                          w.part_pq.as<double>(), tiles0, cur,
                          w.part_rr.as<double>(), ss);
+        if (mixed) {
+            // FP32 V-cycle: gate and narrowing, V-cycle, widening with the
+            // partials of r . z and z . q for the flexible beta
+            float* r32 = w.r32.as<float>();
+            float* z32 = w.z32.as<float>();
+            launch_vc_enter(st, active, sl, nact, w.part_rr.as<double>(), vb, n,
+                            r, r32, ss);
+            vcycle(p, 0, nact, sl, active, (const float*)r32, z32, CycleCtl(),
+                   ss);
+            launch_vc_exit(sl, active, nact, n, tiles0, z32, z, r, q,
+                           w.part_rz.as<double>(), w.part_zq.as<double>(), ss);
+            return;
+        }
         CycleCtl c;
         c.gate = 1;
         c.st = st;
@@ -999,7 +1125,7 @@ rls_status rls_solve_sweep(rls_problem* p, const double* b, const double* lam,
         c.nrr = vb;
         c.dot_part = w.part_rz.as<double>();
         c.dot_stride = tiles0;
-        vcycle(p, 0, nact, sl, active, r, z, c, ss);
+        vcycle(p, 0, nact, sl, active, (const double*)r, z, c, ss);
     };
 
     // Iterate in chunks of `chunk` iterations (even, so that the p buffers
@@ -1098,7 +1224,8 @@ rls_status rls_solve_sweep(rls_problem* p, const double* b, const double* lam,
         // with at least one active slot also reads the three shared stencil
         // planes (24 bytes per pixel).
         const int nu0 = p->nu[0];
-        const int per_cycle = (p->kt > 0 && nu0 >= 2) ? 2 * nu0 - 3 : 0;
+        const int per_cycle =
+            (p->kt > 0 && nu0 >= 2 && p->prec == RLS_PREC_FP64) ? 2 * nu0 - 3 : 0;
         double slot_launches = 0.0;
         int max_cycles = 0;
         for (int i = 0; i < ns; ++i) {

@@ -28,37 +28,51 @@
 
 namespace rls {
 
-__device__ __forceinline__ double ldu(const double* base, uint32_t idx);
+// Element idx of an array with a workgroup-uniform base: a 32-bit byte
+// offset on a scalar base (grids are limited to 2^28 points per slot).
+template <class R>
+__device__ __forceinline__ R ldu(const R* base, uint32_t idx) {
+    return *reinterpret_cast<const R*>(reinterpret_cast<const char*>(base) +
+                                       idx * (uint32_t)sizeof(R));
+}
+template <class R>
+__device__ __forceinline__ void stu(R* base, uint32_t idx, R v) {
+    *reinterpret_cast<R*>(reinterpret_cast<char*>(base) +
+                          idx * (uint32_t)sizeof(R)) = v;
+}
 
-__device__ __forceinline__ double diag_at(const LevelGeom& g, double l2,
-                                          int i, int j, uint32_t p) {
+template <class R>
+__device__ __forceinline__ R diag_at(const LevelGeomT<R>& g, R l2, int i,
+                                     int j, uint32_t p) {
     return g.gv.diag[i] * g.gh.diag[j] + l2 * ldu(g.S.c, p);
 }
 
 // Coarse points contributing to fine point f and their weights (linear
 // interpolation, vertex-centred).
+template <class R>
 __device__ __forceinline__ int interp_sources(int f, int nf, int periodic,
-                                              int* I, double* w) {
+                                              int* I, R* w) {
     const int nc = nf >> 1;
-    if ((f & 1) == 0) { I[0] = f >> 1; w[0] = 1.0; return 1; }
+    if ((f & 1) == 0) { I[0] = f >> 1; w[0] = R(1); return 1; }
     const int c = f >> 1;
-    if (c + 1 < nc) { I[0] = c; I[1] = c + 1; w[0] = w[1] = 0.5; return 2; }
-    if (periodic) { I[0] = c; I[1] = 0; w[0] = w[1] = 0.5; return 2; }
-    I[0] = c; w[0] = 1.0; return 1;
+    if (c + 1 < nc) { I[0] = c; I[1] = c + 1; w[0] = w[1] = R(0.5); return 2; }
+    if (periodic) { I[0] = c; I[1] = 0; w[0] = w[1] = R(0.5); return 2; }
+    I[0] = c; w[0] = R(1); return 1;
 }
 
 // (P e)(fi, fj) for the coarse vector e of size (nf_v/2) x (nf_h/2).
-__device__ __forceinline__ double prolong_at(const double* __restrict__ e,
-                                             int fi, int fj, int nvf, int nhf,
-                                             int periodic) {
+template <class R>
+__device__ __forceinline__ R prolong_at(const R* __restrict__ e, int fi,
+                                        int fj, int nvf, int nhf,
+                                        int periodic) {
     int Ii[2], Jj[2];
-    double wi[2], wj[2];
+    R wi[2], wj[2];
     const int ni = interp_sources(fi, nvf, periodic, Ii, wi);
     const int nj = interp_sources(fj, nhf, periodic, Jj, wj);
     const int64_t nvc = nvf >> 1;
-    double s = 0.0;
+    R s = R(0);
     for (int b = 0; b < nj; ++b) {
-        double cs = 0.0;
+        R cs = R(0);
         for (int a = 0; a < ni; ++a) cs += wi[a] * e[Ii[a] + nvc * Jj[b]];
         s += wj[b] * cs;
     }
@@ -98,7 +112,8 @@ struct TileShape {
     int SR;                 // column stride of the staged K v
     int WV, WVP, WH, WHP;   // tap counts, padded to CH
     int NCV, NCH;           // staged coefficient lines (1: uniform band)
-    __host__ __device__ TileShape(const LevelGeom& g, int ext) {
+    template <class R>
+    __host__ __device__ TileShape(const LevelGeomT<R>& g, int ext) {
         lo = ext;
         bwv = g.gv.bw;
         bwh = g.gh.bw;
@@ -124,19 +139,21 @@ struct TileShape {
         NCH = g.gh.uniform ? 1 : NWH * HWIN;
     }
     // the horizontal-pass result, reused for K v (and the residual)
-    __host__ __device__ size_t ht_doubles() const {
+    __host__ __device__ size_t ht_elems() const {
         const size_t x = (size_t)CO * SH, y = (size_t)CO * SR;
         return x > y ? x : y;
     }
-    __host__ __device__ size_t lds_doubles() const {
-        return (size_t)RY * SX + ht_doubles() + (size_t)NCV * WVP +
+    // LDS elements (of the level's value type)
+    __host__ __device__ size_t lds_elems() const {
+        return (size_t)RY * SX + ht_elems() + (size_t)NCV * WVP +
                (size_t)NCH * WHP + RO + CO;
     }
 };
 
 // Grid point of output e, false outside the grid.
+template <class R>
 __device__ __forceinline__ bool out_index(int e, const TileShape& T,
-                                          const LevelGeom& g, int i0, int j0,
+                                          const LevelGeomT<R>& g, int i0, int j0,
                                           int& gi, int& gj) {
     const int nv = g.nv, nh = g.nh, per = g.S.periodic;
     const int c = e / T.RO, r = e - c * T.RO;
@@ -149,41 +166,34 @@ __device__ __forceinline__ bool out_index(int e, const TileShape& T,
     return true;
 }
 
-// Element idx of an array with a workgroup-uniform base: a 32-bit byte
-// offset on a scalar base (grids are limited to 2^28 points per slot).
-__device__ __forceinline__ double ldu(const double* base, uint32_t idx) {
-    return *reinterpret_cast<const double*>(
-        reinterpret_cast<const char*>(base) + (idx << 3));
-}
-__device__ __forceinline__ void stu(double* base, uint32_t idx, double v) {
-    *reinterpret_cast<double*>(reinterpret_cast<char*>(base) + (idx << 3)) = v;
-}
-
 // The slot's arrays (uniform over the workgroup).
+template <class R>
 struct SlotPtrs {
-    const double* src;   // operand v (or z for the p update)
-    const double* pold;  // previous search direction
-    const double* f;     // right-hand side
-    double* d;           // Chebyshev direction
-    double* out;         // result
-    double* pnew;        // new search direction
+    const R* src;   // operand v (or z for the p update)
+    const R* pold;  // previous search direction
+    const R* f;     // right-hand side
+    R* d;           // Chebyshev direction
+    R* out;         // result
+    R* pnew;        // new search direction
 };
 
 // Operands of one output point from global memory, requested before the
 // tile load so that they arrive with it: right-hand side and Chebyshev
 // direction (per lambda) and the five-point part of the stencil (centre,
 // north, south, east, west couplings; zero across a non-periodic edge).
+template <class R>
 struct OutPre {
-    double f, d, sc, sn, ss, se, sw;
+    R f, d, sc, sn, ss, se, sw;
 };
 
-template <int PRO, int EPI>
-__device__ __forceinline__ void out_load(OutPre& q, int e, const ApplyArgs& a,
-                                         const SlotPtrs& sp, const TileShape& T,
-                                         int i0, int j0) {
-    const LevelGeom& g = a.g;
+template <int PRO, int EPI, class R>
+__device__ __forceinline__ void out_load(OutPre<R>& q, int e,
+                                         const ApplyArgsT<R>& a,
+                                         const SlotPtrs<R>& sp,
+                                         const TileShape& T, int i0, int j0) {
+    const LevelGeomT<R>& g = a.g;
     const int nv = g.nv, nh = g.nh, per = g.S.periodic;
-    q.f = q.d = q.sc = q.sn = q.ss = q.se = q.sw = 0.0;
+    q.f = q.d = q.sc = q.sn = q.ss = q.se = q.sw = R(0);
     int gi, gj;
     if (!out_index(e, T, g, i0, j0, gi, gj)) return;
     const uint32_t p = gi + (uint32_t)nv * gj;
@@ -201,27 +211,24 @@ __device__ __forceinline__ void out_load(OutPre& q, int e, const ApplyArgs& a,
 }
 
 // Stencil term and epilogue at output e; K v's Gram part is staged in kvs.
-template <int PRO, int EPI>
-__device__ __forceinline__ void out_point(const OutPre& q, int e,
-                                          const ApplyArgs& a,
-                                          const SlotPtrs& sp,
-                                          const TileShape& T,
-                                          const double* vin, double* kvs,
-                                          double l2,
-                                          const double* dgl, double c0,
-                                          double c1, int i0, int j0,
-                                          double& dot) {
+template <int PRO, int EPI, class R>
+__device__ __forceinline__ void out_point(const OutPre<R>& q, int e,
+                                          const ApplyArgsT<R>& a,
+                                          const SlotPtrs<R>& sp,
+                                          const TileShape& T, const R* vin,
+                                          R* kvs, R l2, const R* dgl, R c0,
+                                          R c1, int i0, int j0, double& dot) {
     const int c = e / T.RO, r = e - c * T.RO;
-    const LevelGeom& g = a.g;
+    const LevelGeomT<R>& g = a.g;
     int gi, gj;
     if (!out_index(e, T, g, i0, j0, gi, gj)) {
-        if (EPI == EPI_RESTRICT) kvs[c * T.SR + r] = 0.0;
+        if (EPI == EPI_RESTRICT) kvs[c * T.SR + r] = R(0);
         return;
     }
     const int nv = g.nv, nh = g.nh, per = g.S.periodic;
     const uint32_t p = gi + (uint32_t)nv * gj;
-    const double* vc = vin + (r - T.lo + T.hv) * T.SX + c - T.lo + T.hh;
-    double sv = q.sc * vc[0];
+    const R* vc = vin + (r - T.lo + T.hv) * T.SX + c - T.lo + T.hh;
+    R sv = q.sc * vc[0];
     sv += q.sn * vc[T.SX];
     sv += q.ss * vc[-T.SX];
     sv += q.se * vc[1];
@@ -236,30 +243,30 @@ __device__ __forceinline__ void out_point(const OutPre& q, int e,
         sv += ldu(g.S.cse, p) * vc[-T.SX + 1];
         if (okip && okjm) sv += ldu(g.S.cse, ip + (uint32_t)nv * jm) * vc[T.SX - 1];
     }
-    const double kv = kvs[c * T.SR + r] + l2 * sv;
-    const double v = vc[0];
+    const R kv = kvs[c * T.SR + r] + l2 * sv;
+    const R v = vc[0];
     if (EPI == EPI_STORE) {
         stu(sp.out, p, kv);
     } else if (EPI == EPI_DOT) {
         stu(sp.out, p, kv);
-        dot += v * kv;
+        dot += (double)v * (double)kv;
     } else if (EPI == EPI_RESID) {
         stu(sp.out, p, q.f - kv);
     } else if (EPI == EPI_RESTRICT) {
         kvs[c * T.SR + r] = q.f - kv;
     } else {   // EPI_CHEB
-        const double dg = dgl[r] * dgl[T.RO + c] + l2 * q.sc;
-        const double dprev = PRO == PRO_JACOBI ? v : q.d;
-        const double dn = c0 * dprev + c1 * (q.f - kv) / dg;
+        const R dg = dgl[r] * dgl[T.RO + c] + l2 * q.sc;
+        const R dprev = PRO == PRO_JACOBI ? v : q.d;
+        const R dn = c0 * dprev + c1 * (q.f - kv) / dg;
         stu(sp.d, p, dn);
-        const double xn = v + dn;
+        const R xn = v + dn;
         stu(sp.out, p, xn);
-        if (a.dot) dot += q.f * xn;
+        if (a.dot) dot += (double)q.f * (double)xn;
     }
 }
 
-template <int PRO, int EPI>
-__device__ __forceinline__ void apply_body(const ApplyArgs& a, double* lds,
+template <int PRO, int EPI, class R>
+__device__ __forceinline__ void apply_body(const ApplyArgsT<R>& a, R* lds,
                                            double* red) {
     constexpr int EXT = EPI == EPI_RESTRICT ? 1 : 0;
     constexpr int NT = APPLY_THREADS;
@@ -272,7 +279,7 @@ __device__ __forceinline__ void apply_body(const ApplyArgs& a, double* lds,
     const bool act = !a.active || a.active[slot];
     constexpr bool SCALARS = PRO == PRO_PUPDATE;
     if ((SCALARS || a.gate) && !act) return;
-    const LevelGeom& g = a.g;
+    const LevelGeomT<R>& g = a.g;
     const int nv = g.nv, nh = g.nh;
     const int64_t n = (int64_t)nv * nh;
     // XCD-aware tile order: workgroups are dealt round-robin over the 8
@@ -284,29 +291,30 @@ __device__ __forceinline__ void apply_body(const ApplyArgs& a, double* lds,
     const int tx = tile % ntx, ty = tile / ntx;
     const int i0 = tx * TILE_Y, j0 = ty * TILE_X;
     const TileShape T(g, EXT);
-    double* vin = lds;
-    double* ht = vin + (size_t)T.RY * T.SX;
-    double* kvs = ht;                      // after the vertical pass
-    double* cv = ht + T.ht_doubles();
-    double* ch = cv + (size_t)T.NCV * T.WVP;
-    double* dgl = ch + (size_t)T.NCH * T.WHP;   // diag G_v rows, diag G_h cols
+    R* vin = lds;
+    R* ht = vin + (size_t)T.RY * T.SX;
+    R* kvs = ht;                      // after the vertical pass
+    R* cv = ht + T.ht_elems();
+    R* ch = cv + (size_t)T.NCV * T.WVP;
+    R* dgl = ch + (size_t)T.NCH * T.WHP;   // diag G_v rows, diag G_h cols
     const size_t so = (size_t)slot * n;
-    SlotPtrs sp;
+    SlotPtrs<R> sp;
     sp.src = a.in ? a.in + so : nullptr;
     sp.pold = a.pold ? a.pold + so : nullptr;
     sp.f = a.f ? (a.f_shared ? a.f : a.f + so) : nullptr;
     sp.d = a.d ? a.d + so : nullptr;
     sp.out = a.out ? a.out + so : nullptr;
     sp.pnew = a.pnew ? a.pnew + so : nullptr;
-    const double l2 = a.lam2[slot];
+    const R l2 = (R)a.lam2[slot];
     const int per = g.S.periodic;
 
     // PCG scalars folded into this kernel; tile 0 of a slot leads
     const bool lead = tile == 0;
-    double beta = 0.0, cj = 0.0;
+    double beta = 0.0;
+    R cj = R(0);
     if (PRO == PRO_PUPDATE) {
         if (!pcg_beta<NT>(a.st, a.active_w, slot, a.part_rz, a.nrz, a.parity,
-                          lead, red, beta))
+                          a.flex ? a.part_zq : nullptr, lead, red, beta))
             return;
     }
     if (a.gate) {
@@ -314,11 +322,11 @@ __device__ __forceinline__ void apply_body(const ApplyArgs& a, double* lds,
             return;
     }
     if (PRO == PRO_JACOBI || PRO == PRO_PROLONG_JAC)
-        cj = a.cheb_first[(size_t)slot * a.cheb_stride + 1];
-    double c0 = 0.0, c1 = 0.0;
+        cj = (R)a.cheb_first[(size_t)slot * a.cheb_stride + 1];
+    R c0 = R(0), c1 = R(0);
     if (EPI == EPI_CHEB) {
-        c0 = a.cheb[(size_t)slot * a.cheb_stride];
-        c1 = a.cheb[(size_t)slot * a.cheb_stride + 1];
+        c0 = (R)a.cheb[(size_t)slot * a.cheb_stride];
+        c1 = (R)a.cheb[(size_t)slot * a.cheb_stride + 1];
     }
 
     // 1. everything the tile needs from global memory is requested before
@@ -326,7 +334,7 @@ __device__ __forceinline__ void apply_body(const ApplyArgs& a, double* lds,
     //    plus halo with the prologue applied (batches of LB loads per
     //    thread, no store in between), and the per-output operands of the
     //    epilogue, which stay in flight through the band passes.
-    double tapv = 0.0, taph = 0.0, dgt = 0.0;
+    R tapv = R(0), taph = R(0), dgt = R(0);
     if (g.gv.uniform && t < T.WV) tapv = g.gv.taps[t];
     if (g.gh.uniform && t < T.WH) taph = g.gh.taps[t];
     if (EPI == EPI_CHEB && t < T.RO + T.CO) {
@@ -344,7 +352,7 @@ __device__ __forceinline__ void apply_body(const ApplyArgs& a, double* lds,
     constexpr int LB = PRO == PRO_PLAIN || PRO == PRO_PUPDATE ? 24
                        : PRO == PRO_JACOBI                      ? 12
                                                                 : 6;
-    OutPre pre[NPRE];
+    OutPre<R> pre[NPRE];
     const int il = t & (RL - 1), jl = t / RL;
     for (int rb = 0; rb < T.RY; rb += RL) {
         const int ii = rb + il;
@@ -353,11 +361,11 @@ __device__ __forceinline__ void apply_body(const ApplyArgs& a, double* lds,
         bool okv;
         const int gi = map_index(ui, nv, g.gv.map, okv);
         for (int cb = 0; cb < T.CX; cb += 2 * LB) {
-            double v[LB];
+            R v[LB];
 #pragma unroll
             for (int u = 0; u < LB; ++u) {
                 const int jj = cb + jl + 2 * u;
-                v[u] = 0.0;
+                v[u] = R(0);
                 bool okh;
                 const int gj = map_index(j0 - T.hh + jj, nh, g.gh.map, okh);
                 if (rin && okv && jj < T.CX && okh) {
@@ -366,8 +374,8 @@ __device__ __forceinline__ void apply_body(const ApplyArgs& a, double* lds,
                         v[u] = ldu(sp.src, p);
                     } else if (PRO == PRO_PUPDATE) {
                         // p_old is undefined before the first iteration
-                        const double po = beta == 0.0 ? 0.0 : ldu(sp.pold, p);
-                        v[u] = ldu(sp.src, p) + beta * po;
+                        const R po = beta == 0.0 ? R(0) : ldu(sp.pold, p);
+                        v[u] = ldu(sp.src, p) + (R)beta * po;
                     } else if (PRO == PRO_JACOBI) {
                         v[u] = cj * ldu(sp.f, p) / diag_at(g, l2, gi, gj, p);
                     } else if (PRO == PRO_PROLONG) {
@@ -384,7 +392,7 @@ __device__ __forceinline__ void apply_body(const ApplyArgs& a, double* lds,
             if (rb == 0 && cb == 0) {
 #pragma unroll
                 for (int k = 0; k < NPRE; ++k)
-                    out_load<PRO, EPI>(pre[k], t + k * NT, a, sp, T, i0, j0);
+                    out_load<PRO, EPI, R>(pre[k], t + k * NT, a, sp, T, i0, j0);
             }
 #pragma unroll
             for (int u = 0; u < LB; ++u) {
@@ -416,7 +424,7 @@ __device__ __forceinline__ void apply_body(const ApplyArgs& a, double* lds,
             const int r = e / T.WVP, k = e - r * T.WVP;
             int gi = i0 + r - T.lo;
             if (gi < 0 && per) gi += nv;
-            double c = 0.0;
+            R c = R(0);
             if (k < T.WV && r < T.RO && gi >= 0 && gi < nv)
                 c = g.gv.table[(size_t)gi * T.WV + k];
             cv[e] = c;
@@ -429,7 +437,7 @@ __device__ __forceinline__ void apply_body(const ApplyArgs& a, double* lds,
             const int c0 = e / T.WHP, k = e - c0 * T.WHP;
             int gj = j0 + c0 - T.lo;
             if (gj < 0 && per) gj += nh;
-            double c = 0.0;
+            R c = R(0);
             if (k < T.WH && c0 < T.CO && gj >= 0 && gj < nh)
                 c = g.gh.table[(size_t)gj * T.WH + k];
             ch[e] = c;
@@ -439,14 +447,14 @@ __device__ __forceinline__ void apply_body(const ApplyArgs& a, double* lds,
         const int pad = T.SX - T.CX;
         for (int e = t; e < T.RY * pad; e += NT) {
             const int ii = e / pad;
-            vin[ii * T.SX + T.CX + (e - ii * pad)] = 0.0;
+            vin[ii * T.SX + T.CX + (e - ii * pad)] = R(0);
         }
     }
     {
         const int pad = T.SH - T.NHR;
         for (int e = t; e < T.CO * pad; e += NT) {
             const int c = e / pad, q = T.NHR + (e - c * pad);
-            ht[c * T.SH + q] = 0.0;
+            ht[c * T.SH + q] = R(0);
         }
     }
     __syncthreads();
@@ -456,30 +464,30 @@ __device__ __forceinline__ void apply_body(const ApplyArgs& a, double* lds,
     for (int e = t; e < T.NHR * T.NWH; e += NT) {
         const int w = e / T.NHR, q = e - w * T.NHR;       // lanes along rows
         const int c0 = w * HWIN;
-        const double* rowp = vin + (q + T.hv - T.lo - T.bwv) * T.SX +
+        const R* rowp = vin + (q + T.hv - T.lo - T.bwv) * T.SX +
                              (c0 - T.lo + T.hh - T.bwh);
-        double acc[HWIN];
+        R acc[HWIN];
 #pragma unroll
-        for (int o = 0; o < HWIN; ++o) acc[o] = 0.0;
+        for (int o = 0; o < HWIN; ++o) acc[o] = R(0);
         if (g.gh.uniform) {
             for (int k0 = 0; k0 < T.WHP; k0 += CH) {
-                double win[HWIN + CH - 1];
+                R win[HWIN + CH - 1];
 #pragma unroll
                 for (int m = 0; m < HWIN + CH - 1; ++m)
                     win[m] = rowp[k0 + m];
 #pragma unroll
                 for (int k = 0; k < CH; ++k) {
-                    const double tp = ch[k0 + k];
+                    const R tp = ch[k0 + k];
 #pragma unroll
                     for (int o = 0; o < HWIN; ++o) acc[o] += tp * win[o + k];
                 }
             }
         } else {
             // per-column coefficients: rotating window, one tap at a time
-            double win[HWIN];
+            R win[HWIN];
 #pragma unroll
             for (int m = 0; m < HWIN; ++m) win[m] = rowp[m];
-            const double* cf = ch + c0 * T.WHP;
+            const R* cf = ch + c0 * T.WHP;
             for (int k = 0; k < T.WH; ++k) {
 #pragma unroll
                 for (int o = 0; o < HWIN; ++o) acc[o] += cf[o * T.WHP + k] * win[o];
@@ -495,31 +503,31 @@ __device__ __forceinline__ void apply_body(const ApplyArgs& a, double* lds,
     __syncthreads();
 
     // 3. vertical pass of G_v: (G v)(r, c) = sum_k G_v(r, k) ht(r + k, c)
-    double vacc[VWIN];
+    R vacc[VWIN];
     const int vw = t / T.CO, vcol = t - vw * T.CO;        // lanes along columns
     const bool vown = t < T.CO * T.NWV;
     if (vown) {
         const int r0 = vw * VWIN;
-        const double* colp = ht + vcol * T.SH + r0;
+        const R* colp = ht + vcol * T.SH + r0;
 #pragma unroll
-        for (int o = 0; o < VWIN; ++o) vacc[o] = 0.0;
+        for (int o = 0; o < VWIN; ++o) vacc[o] = R(0);
         if (g.gv.uniform) {
             for (int k0 = 0; k0 < T.WVP; k0 += CH) {
-                double win[VWIN + CH - 1];
+                R win[VWIN + CH - 1];
 #pragma unroll
                 for (int m = 0; m < VWIN + CH - 1; ++m) win[m] = colp[k0 + m];
 #pragma unroll
                 for (int k = 0; k < CH; ++k) {
-                    const double tp = cv[k0 + k];
+                    const R tp = cv[k0 + k];
 #pragma unroll
                     for (int o = 0; o < VWIN; ++o) vacc[o] += tp * win[o + k];
                 }
             }
         } else {
-            double win[VWIN];
+            R win[VWIN];
 #pragma unroll
             for (int m = 0; m < VWIN; ++m) win[m] = colp[m];
-            const double* cf = cv + r0 * T.WVP;
+            const R* cf = cv + r0 * T.WVP;
             for (int k = 0; k < T.WV; ++k) {
 #pragma unroll
                 for (int o = 0; o < VWIN; ++o) vacc[o] += cf[o * T.WVP + k] * win[o];
@@ -544,12 +552,12 @@ __device__ __forceinline__ void apply_body(const ApplyArgs& a, double* lds,
     const int nout = T.RO * T.CO;
 #pragma unroll
     for (int k = 0; k < NPRE; ++k)
-        out_point<PRO, EPI>(pre[k], t + k * NT, a, sp, T, vin, kvs, l2, dgl, c0,
+        out_point<PRO, EPI, R>(pre[k], t + k * NT, a, sp, T, vin, kvs, l2, dgl, c0,
                             c1, i0, j0, dot);
     for (int e = t + NPRE * NT; e < nout; e += NT) {
-        OutPre q;
-        out_load<PRO, EPI>(q, e, a, sp, T, i0, j0);
-        out_point<PRO, EPI>(q, e, a, sp, T, vin, kvs, l2, dgl, c0, c1, i0, j0,
+        OutPre<R> q;
+        out_load<PRO, EPI, R>(q, e, a, sp, T, i0, j0);
+        out_point<PRO, EPI, R>(q, e, a, sp, T, vin, kvs, l2, dgl, c0, c1, i0, j0,
                             dot);
     }
 
@@ -557,7 +565,7 @@ __device__ __forceinline__ void apply_body(const ApplyArgs& a, double* lds,
         // full weighting of the residual tile onto the coarse points whose
         // centre lies in the tile: fc(I, J) = sum P(f, (I, J)) res(f)
         __syncthreads();
-        const double* rs = kvs;
+        const R* rs = kvs;
         const int nvc = nv >> 1, nhc = nh >> 1;
         const int I0 = i0 >> 1, J0 = j0 >> 1;
         constexpr int CI = TILE_Y / 2, CJ = TILE_X / 2;
@@ -565,19 +573,19 @@ __device__ __forceinline__ void apply_body(const ApplyArgs& a, double* lds,
             const int cjj = e / CI, cii = e - cjj * CI;
             const int I = I0 + cii, J = J0 + cjj;
             if (I >= nvc || J >= nhc) continue;
-            double s = 0.0;
+            R s = R(0);
             for (int b = -1; b <= 1; ++b) {
                 int fj = 2 * J + b;
                 if (!wrap_or_drop(fj, nh, per)) continue;
-                const double wj = interp_weight(fj, J, nh, per);
-                if (wj == 0.0) continue;
+                const R wj = (R)interp_weight(fj, J, nh, per);
+                if (wj == R(0)) continue;
                 const int lc = 2 * cjj + b + 1;             // local column + lo
-                double cs = 0.0;
+                R cs = R(0);
                 for (int a2 = -1; a2 <= 1; ++a2) {
                     int fi = 2 * I + a2;
                     if (!wrap_or_drop(fi, nv, per)) continue;
-                    const double wi = interp_weight(fi, I, nv, per);
-                    if (wi != 0.0) cs += wi * rs[lc * T.SR + 2 * cii + a2 + 1];
+                    const R wi = (R)interp_weight(fi, I, nv, per);
+                    if (wi != R(0)) cs += wi * rs[lc * T.SR + 2 * cii + a2 + 1];
                 }
                 s += wj * cs;
             }
@@ -598,46 +606,49 @@ __device__ __forceinline__ void apply_body(const ApplyArgs& a, double* lds,
 #define RLS_APPLY_BOUNDS           \
     __launch_bounds__(APPLY_THREADS) \
     __attribute__((amdgpu_waves_per_eu(RLS_APPLY_WAVES)))
+// FP32 tiles use fewer registers: three workgroups per CU (<= 168 VGPRs).
+#define RLS_APPLY_BOUNDS_T(R)      \
+    __launch_bounds__(APPLY_THREADS) \
+    __attribute__((amdgpu_waves_per_eu(sizeof(R) == 4 ? 3 : RLS_APPLY_WAVES)))
 
-template <int PRO, int EPI>
-__global__ void RLS_APPLY_BOUNDS k_apply(ApplyArgs a) {
-    extern __shared__ double lds[];
+template <int PRO, int EPI, class R>
+__global__ void RLS_APPLY_BOUNDS_T(R) k_apply(ApplyArgsT<R> a) {
+    extern __shared__ double lds_raw[];
     __shared__ double red[APPLY_THREADS];
-    apply_body<PRO, EPI>(a, lds, red);
+    apply_body<PRO, EPI, R>(a, reinterpret_cast<R*>(lds_raw), red);
 }
 
 // The finest-level Chebyshev step (plain prologue) under a name of its own,
 // so that profiles separate the sweep's most frequent kernel from the same
 // step on coarser levels.
-__global__ void RLS_APPLY_BOUNDS k_smooth_fine(ApplyArgs a) {
-    extern __shared__ double lds[];
+template <class R>
+__global__ void RLS_APPLY_BOUNDS_T(R) k_smooth_fine(ApplyArgsT<R> a) {
+    extern __shared__ double lds_raw[];
     __shared__ double red[APPLY_THREADS];
-    apply_body<PRO_PLAIN, EPI_CHEB>(a, lds, red);
+    apply_body<PRO_PLAIN, EPI_CHEB, R>(a, reinterpret_cast<R*>(lds_raw), red);
 }
 
-template <int PRO, int EPI>
-static void configure_one() {
-    // dynamic LDS may use what the kernel's static LDS leaves of 160 KiB
+// dynamic LDS may use what the kernel's static LDS leaves of 160 KiB
+static void allow_lds(const void* fn) {
     hipFuncAttributes attr;
     size_t stat = 0;
-    if (hipFuncGetAttributes(&attr, (const void*)k_apply<PRO, EPI>) == hipSuccess)
-        stat = attr.sharedSizeBytes;
-    (void)hipFuncSetAttribute((const void*)k_apply<PRO, EPI>,
-                              hipFuncAttributeMaxDynamicSharedMemorySize,
+    if (hipFuncGetAttributes(&attr, fn) == hipSuccess) stat = attr.sharedSizeBytes;
+    (void)hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize,
                               (int)(160 * 1024 - stat));
 }
 
-template <int PRO, int EPI>
-static void launch_one(const ApplyArgs& a, hipStream_t s) {
+template <int PRO, int EPI, class R>
+static void launch_one(const ApplyArgsT<R>& a, hipStream_t s) {
     const TileShape T(a.g, EPI == EPI_RESTRICT);
     dim3 grid((a.g.nv + TILE_Y - 1) / TILE_Y, (a.g.nh + TILE_X - 1) / TILE_X,
               a.nslot);
-    hipLaunchKernelGGL((k_apply<PRO, EPI>), grid, dim3(APPLY_THREADS),
-                       sizeof(double) * T.lds_doubles(), s, a);
+    hipLaunchKernelGGL((k_apply<PRO, EPI, R>), grid, dim3(APPLY_THREADS),
+                       sizeof(R) * T.lds_elems(), s, a);
 }
 
-// Every (prologue, epilogue) pair in use.
-#define RLS_APPLY_VARIANTS(X)         \
+// Every (prologue, epilogue) pair in use: all of them in FP64, the V-cycle's
+// (and the plain product) in FP32.
+#define RLS_APPLY_VARIANTS_F64(X)     \
     X(PRO_PUPDATE, EPI_DOT)           \
     X(PRO_JACOBI, EPI_CHEB)           \
     X(PRO_JACOBI, EPI_RESTRICT)       \
@@ -648,22 +659,26 @@ static void launch_one(const ApplyArgs& a, hipStream_t s) {
     X(PRO_PLAIN, EPI_RESID)           \
     X(PRO_PLAIN, EPI_RESTRICT)        \
     X(PRO_PLAIN, EPI_CHEB)
+#define RLS_APPLY_VARIANTS_F32(X)     \
+    X(PRO_JACOBI, EPI_CHEB)           \
+    X(PRO_JACOBI, EPI_RESTRICT)       \
+    X(PRO_PROLONG, EPI_CHEB)          \
+    X(PRO_PROLONG_JAC, EPI_CHEB)      \
+    X(PRO_PLAIN, EPI_STORE)           \
+    X(PRO_PLAIN, EPI_RESTRICT)        \
+    X(PRO_PLAIN, EPI_CHEB)
 
 void configure_apply_kernels() {
     static bool done = false;
     if (done) return;
-#define RLS_CFG(P, E) configure_one<P, E>();
-    RLS_APPLY_VARIANTS(RLS_CFG)
-#undef RLS_CFG
-    {
-        hipFuncAttributes attr;
-        size_t stat = 0;
-        if (hipFuncGetAttributes(&attr, (const void*)k_smooth_fine) == hipSuccess)
-            stat = attr.sharedSizeBytes;
-        (void)hipFuncSetAttribute((const void*)k_smooth_fine,
-                                  hipFuncAttributeMaxDynamicSharedMemorySize,
-                                  (int)(160 * 1024 - stat));
-    }
+#define RLS_CFG64(P, E) allow_lds((const void*)k_apply<P, E, double>);
+#define RLS_CFG32(P, E) allow_lds((const void*)k_apply<P, E, float>);
+    RLS_APPLY_VARIANTS_F64(RLS_CFG64)
+    RLS_APPLY_VARIANTS_F32(RLS_CFG32)
+#undef RLS_CFG64
+#undef RLS_CFG32
+    allow_lds((const void*)k_smooth_fine<double>);
+    allow_lds((const void*)k_smooth_fine<float>);
     (void)hipGetLastError();
     done = true;
 }
@@ -674,23 +689,45 @@ int apply_tiles(const LevelGeom& g) {
 
 size_t apply_lds_bytes(const LevelGeom& g, int epi) {
     const TileShape T(g, epi == EPI_RESTRICT);
-    return sizeof(double) * T.lds_doubles();
+    return sizeof(double) * T.lds_elems();
 }
 
-void launch_smooth_fine(const ApplyArgs& a, hipStream_t s) {
+size_t apply_lds_bytes(const LevelGeomT<float>& g, int epi) {
+    const TileShape T(g, epi == EPI_RESTRICT);
+    return sizeof(float) * T.lds_elems();
+}
+
+template <class R>
+static void smooth_fine_impl(const ApplyArgsT<R>& a, hipStream_t s) {
     const TileShape T(a.g, 0);
     dim3 grid((a.g.nv + TILE_Y - 1) / TILE_Y, (a.g.nh + TILE_X - 1) / TILE_X,
               a.nslot);
-    hipLaunchKernelGGL(k_smooth_fine, grid, dim3(APPLY_THREADS),
-                       sizeof(double) * T.lds_doubles(), s, a);
+    hipLaunchKernelGGL(k_smooth_fine<R>, grid, dim3(APPLY_THREADS),
+                       sizeof(R) * T.lds_elems(), s, a);
+}
+void launch_smooth_fine(const ApplyArgsT<double>& a, hipStream_t s) {
+    smooth_fine_impl(a, s);
+}
+void launch_smooth_fine(const ApplyArgsT<float>& a, hipStream_t s) {
+    smooth_fine_impl(a, s);
 }
 
-void launch_apply(int pro, int epi, const ApplyArgs& a, hipStream_t s) {
+void launch_apply(int pro, int epi, const ApplyArgsT<double>& a, hipStream_t s) {
 #define RLS_LAUNCH(P, E) \
-    if (pro == P && epi == E) { launch_one<P, E>(a, s); return; }
-    RLS_APPLY_VARIANTS(RLS_LAUNCH)
+    if (pro == P && epi == E) { launch_one<P, E, double>(a, s); return; }
+    RLS_APPLY_VARIANTS_F64(RLS_LAUNCH)
 #undef RLS_LAUNCH
-    std::fprintf(stderr, "rls: no level-operator kernel for prologue %d, "
+    std::fprintf(stderr, "rls: no FP64 level-operator kernel for prologue %d, "
+                         "epilogue %d\n", pro, epi);
+    std::abort();
+}
+
+void launch_apply(int pro, int epi, const ApplyArgsT<float>& a, hipStream_t s) {
+#define RLS_LAUNCH(P, E) \
+    if (pro == P && epi == E) { launch_one<P, E, float>(a, s); return; }
+    RLS_APPLY_VARIANTS_F32(RLS_LAUNCH)
+#undef RLS_LAUNCH
+    std::fprintf(stderr, "rls: no FP32 level-operator kernel for prologue %d, "
                          "epilogue %d\n", pro, epi);
     std::abort();
 }

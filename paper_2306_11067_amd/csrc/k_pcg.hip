@@ -199,6 +199,71 @@ k_reduce_slots(const double* __restrict__ part, int nparts,
     if (threadIdx.x == 0) out[slot] = s;
 }
 
+// ---- boundary of the FP32 V-cycle under flexible FP64 PCG ---------------
+
+// Narrowing copy dst = (float) src over nslot slots (slot list optional).
+__global__ void __launch_bounds__(VB)
+k_to_f32(const double* __restrict__ src, int64_t n, const int* slots,
+         float* __restrict__ dst) {
+    const int slot = slots ? slots[blockIdx.y] : (int)blockIdx.y;
+    const size_t base = (size_t)slot * n;
+    const int64_t p0 = (int64_t)blockIdx.x * VCHUNK + threadIdx.x;
+#pragma unroll
+    for (int k = 0; k < VPT; ++k) {
+        const int64_t p = p0 + (int64_t)k * VB;
+        if (p < n) dst[base + p] = (float)src[base + p];
+    }
+}
+
+// Convergence test on ||r|| (as the FP64 path does in its first V-cycle
+// kernel), then r32 = (float) r for the V-cycle.
+__global__ void __launch_bounds__(VB)
+k_vc_enter(SlotState* st, int* active, const int* slots, const double* part_rr,
+           int nrr, int64_t n, const double* __restrict__ r,
+           float* __restrict__ r32) {
+    __shared__ double sh[VB];
+    const int slot = slots ? slots[blockIdx.y] : (int)blockIdx.y;
+    if (!active[slot]) return;
+    if (!pcg_gate<VB>(st, active, slot, part_rr, nrr, blockIdx.x == 0, sh))
+        return;
+    const size_t base = (size_t)slot * n;
+    const int64_t p0 = (int64_t)blockIdx.x * VCHUNK + threadIdx.x;
+#pragma unroll
+    for (int k = 0; k < VPT; ++k) {
+        const int64_t p = p0 + (int64_t)k * VB;
+        if (p < n) r32[base + p] = (float)r[base + p];
+    }
+}
+
+// z = (double) z32 and the partials of r . z and z . q ([slot][part], npart
+// parts of n / npart consecutive points each).
+__global__ void __launch_bounds__(VB)
+k_vc_exit(const int* slots, const int* active, int64_t n, int npart,
+          const float* __restrict__ z32, double* __restrict__ z,
+          const double* __restrict__ r, const double* __restrict__ q,
+          double* part_rz, double* part_zq) {
+    __shared__ double sh[VB];
+    const int slot = slots ? slots[blockIdx.y] : (int)blockIdx.y;
+    if (active && !active[slot]) return;
+    const size_t base = (size_t)slot * n;
+    const int64_t len = (n + npart - 1) / npart;
+    const int64_t lo = (int64_t)blockIdx.x * len;
+    const int64_t hi = lo + len < n ? lo + len : n;
+    double rz = 0.0, zq = 0.0;
+    for (int64_t p = lo + threadIdx.x; p < hi; p += VB) {
+        const double zv = (double)z32[base + p];
+        z[base + p] = zv;
+        rz += r[base + p] * zv;
+        if (q) zq += zv * q[base + p];
+    }
+    const double a = block_sum<VB>(rz, sh);
+    if (threadIdx.x == 0) part_rz[(size_t)slot * npart + blockIdx.x] = a;
+    if (part_zq) {
+        const double b = block_sum<VB>(zq, sh);
+        if (threadIdx.x == 0) part_zq[(size_t)slot * npart + blockIdx.x] = b;
+    }
+}
+
 static inline int nblk(int64_t n, int b) { return (int)((n + b - 1) / b); }
 
 void launch_broadcast(const double* src, int64_t n, int nslot, double* dst,
@@ -252,6 +317,27 @@ void launch_reduce_slots(const double* part, int nparts, int nslot,
                          double* out, hipStream_t s) {
     hipLaunchKernelGGL(k_reduce_slots, dim3(nslot), dim3(VB), 0, s, part,
                        nparts, out);
+}
+
+void launch_to_f32(const double* src, int64_t n, int nslot, const int* slots,
+                   float* dst, hipStream_t s) {
+    hipLaunchKernelGGL(k_to_f32, dim3(vec_blocks(n), nslot), dim3(VB), 0, s,
+                       src, n, slots, dst);
+}
+
+void launch_vc_enter(SlotState* st, int* active, const int* slots, int nslot,
+                     const double* part_rr, int nrr, int64_t n, const double* r,
+                     float* r32, hipStream_t s) {
+    hipLaunchKernelGGL(k_vc_enter, dim3(vec_blocks(n), nslot), dim3(VB), 0, s,
+                       st, active, slots, part_rr, nrr, n, r, r32);
+}
+
+void launch_vc_exit(const int* slots, const int* active, int nslot, int64_t n,
+                    int npart, const float* z32, double* z, const double* r,
+                    const double* q, double* part_rz, double* part_zq,
+                    hipStream_t s) {
+    hipLaunchKernelGGL(k_vc_exit, dim3(npart, nslot), dim3(VB), 0, s, slots,
+                       active, n, npart, z32, z, r, q, part_rz, part_zq);
 }
 
 }  // namespace rls

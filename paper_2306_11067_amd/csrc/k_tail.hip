@@ -122,7 +122,8 @@ __device__ void tail_smooth(const TailLevel& L, double l2, int per, int nu,
     }
 }
 
-__global__ void __launch_bounds__(TAIL_THREADS) k_tail(TailArgs a) {
+template <class IO>
+__global__ void __launch_bounds__(TAIL_THREADS) k_tail(TailArgsT<IO> a) {
     extern __shared__ double lds[];
     __shared__ double red[TAIL_THREADS];
     const int slot = a.slots ? a.slots[blockIdx.x] : (int)blockIdx.x;
@@ -156,7 +157,7 @@ __global__ void __launch_bounds__(TAIL_THREADS) k_tail(TailArgs a) {
     sc.res = q + 3 * nt;
 
     for (int p = threadIdx.x; p < n0; p += TAIL_THREADS)
-        F[0][p] = a.f[(size_t)slot * n0 + p];
+        F[0][p] = (double)a.f[(size_t)slot * n0 + p];
     __syncthreads();
 
     // down: smooth, residual, restrict
@@ -255,7 +256,7 @@ __global__ void __launch_bounds__(TAIL_THREADS) k_tail(TailArgs a) {
     double dot = 0.0;
     for (int p = threadIdx.x; p < n0; p += TAIL_THREADS) {
         const double zv = X[0][p];
-        a.z[(size_t)slot * n0 + p] = zv;
+        a.z[(size_t)slot * n0 + p] = (IO)zv;
         dot += F[0][p] * zv;
     }
     if (a.dot) {
@@ -265,29 +266,40 @@ __global__ void __launch_bounds__(TAIL_THREADS) k_tail(TailArgs a) {
     }
 }
 
-size_t tail_lds_bytes(const TailArgs& a) {
+template <class IO>
+size_t tail_lds_bytes(const TailArgsT<IO>& a) {
     size_t d = 0;
     for (int k = 0; k < a.nlev; ++k) d += 2 * (size_t)a.lev[k].nv * a.lev[k].nh;
     const size_t n0 = (size_t)a.lev[0].nv * a.lev[0].nh;
     d += 4 * (n0 > (size_t)TAIL_THREADS ? n0 : (size_t)TAIL_THREADS);
     return d * sizeof(double);
 }
+template size_t tail_lds_bytes(const TailArgsT<double>&);
+template size_t tail_lds_bytes(const TailArgsT<float>&);
 
-void launch_tail(const TailArgs& a, int nslot, hipStream_t s) {
+template <class IO>
+static void tail_impl(const TailArgsT<IO>& a, int nslot, hipStream_t s) {
     static bool configured = false;
     if (!configured) {
         hipFuncAttributes attr;
         size_t stat = 0;
-        if (hipFuncGetAttributes(&attr, (const void*)k_tail) == hipSuccess)
+        if (hipFuncGetAttributes(&attr, (const void*)k_tail<IO>) == hipSuccess)
             stat = attr.sharedSizeBytes;
-        hipFuncSetAttribute((const void*)k_tail,
-                            hipFuncAttributeMaxDynamicSharedMemorySize,
-                            (int)(160 * 1024 - stat));
-        hipGetLastError();
+        (void)hipFuncSetAttribute((const void*)k_tail<IO>,
+                                  hipFuncAttributeMaxDynamicSharedMemorySize,
+                                  (int)(160 * 1024 - stat));
+        (void)hipGetLastError();
         configured = true;
     }
-    hipLaunchKernelGGL(k_tail, dim3(nslot), dim3(TAIL_THREADS), tail_lds_bytes(a),
-                       s, a);
+    hipLaunchKernelGGL(k_tail<IO>, dim3(nslot), dim3(TAIL_THREADS),
+                       tail_lds_bytes(a), s, a);
+}
+
+void launch_tail(const TailArgsT<double>& a, int nslot, hipStream_t s) {
+    tail_impl(a, nslot, s);
+}
+void launch_tail(const TailArgsT<float>& a, int nslot, hipStream_t s) {
+    tail_impl(a, nslot, s);
 }
 
 }  // namespace rls

@@ -40,13 +40,18 @@ __device__ __forceinline__ void stop_slot(SlotState* st, int* active, int slot,
 }
 
 // gamma_k = r_k . z_k from the V-cycle partials; beta_k = gamma_k /
-// gamma_{k-1} (0 at the first iteration).  Returns false when the slot
+// gamma_{k-1} (0 at the first iteration).  With part_zq (flexible CG, for a
+// preconditioner that is not exactly the same linear map at every
+// iteration) the Polak-Ribiere form z_k . (r_k - r_{k-1}) / gamma_{k-1} is
+// used; since r_k - r_{k-1} = -alpha_{k-1} q_{k-1} it equals
+// -alpha_{k-1} (z_k . q_{k-1}) / gamma_{k-1}.  Returns false when the slot
 // stops (r . z not positive or not finite).
 template <int BLOCK>
 __device__ __forceinline__ bool pcg_beta(SlotState* st, int* active, int slot,
                                          const double* part_rz, int nrz,
-                                         int parity, bool leader_block,
-                                         double* sh, double& beta) {
+                                         int parity, const double* part_zq,
+                                         bool leader_block, double* sh,
+                                         double& beta) {
     const double g = block_sum_parts<BLOCK>(part_rz + (size_t)slot * nrz, nrz, sh);
     const bool lead = leader_block && threadIdx.x == 0;
     if (!isfinite(g) || !(g > 0.0)) {
@@ -54,7 +59,15 @@ __device__ __forceinline__ bool pcg_beta(SlotState* st, int* active, int slot,
                             isfinite(g) ? RLS_FLAG_BREAKDOWN : RLS_FLAG_NONFINITE);
         return false;
     }
-    beta = st[slot].it == 0 ? 0.0 : g / st[slot].gam[parity];
+    if (st[slot].it == 0) {
+        beta = 0.0;
+    } else if (part_zq) {
+        const double zq =
+            block_sum_parts<BLOCK>(part_zq + (size_t)slot * nrz, nrz, sh);
+        beta = -st[slot].alpha * zq / st[slot].gam[parity];
+    } else {
+        beta = g / st[slot].gam[parity];
+    }
     if (lead) st[slot].gam[1 - parity] = g;
     return true;
 }

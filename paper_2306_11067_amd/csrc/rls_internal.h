@@ -18,35 +18,43 @@ enum MapKind : int { MAP_ZERO = 0, MAP_WRAP = 1, MAP_REFLECT = 2 };
 // [-bw, bw] is the coefficient of x(map(r + k)).  `uniform` rows all equal
 // `taps` (the index map supplies the boundary); otherwise `table` holds
 // every row, with zeros where r + k falls outside a non-wrapping axis.
-struct BandDev {
+// R is the value type (double; float copies serve the FP32 V-cycle).
+template <class R>
+struct BandDevT {
     int n = 0;
     int bw = 0;
     int map = MAP_ZERO;
     int uniform = 0;
-    const double* taps = nullptr;   // 2bw+1
-    const double* table = nullptr;  // n * (2bw+1)
-    const double* diag = nullptr;   // n
-    const double* rowabs = nullptr; // n: sum_k |row r|
+    const R* taps = nullptr;    // 2bw+1
+    const R* table = nullptr;   // n * (2bw+1)
+    const R* diag = nullptr;    // n
+    const R* rowabs = nullptr;  // n: sum_k |row r|
 };
 
 // Galerkin stencil of L^T D^2 L on one level, five planes of n values:
 // c (centre), cn (i+1, j), ce (i, j+1), cne (i+1, j+1), cse (i-1, j+1).
-struct StencilDev {
-    const double* c = nullptr;
-    const double* cn = nullptr;
-    const double* ce = nullptr;
-    const double* cne = nullptr;
-    const double* cse = nullptr;
-    const double* rowabs = nullptr;  // sum_j |S_ij|
-    int nine = 0;                    // 0: cne/cse are identically zero
+template <class R>
+struct StencilDevT {
+    const R* c = nullptr;
+    const R* cn = nullptr;
+    const R* ce = nullptr;
+    const R* cne = nullptr;
+    const R* cse = nullptr;
+    const R* rowabs = nullptr;  // sum_j |S_ij|
+    int nine = 0;               // 0: cne/cse are identically zero
     int periodic = 0;
 };
 
-struct LevelGeom {
+template <class R>
+struct LevelGeomT {
     int nv = 0, nh = 0;
-    BandDev gv, gh;                  // separable Gram G_h (x) G_v
-    StencilDev S;
+    BandDevT<R> gv, gh;         // separable Gram G_h (x) G_v
+    StencilDevT<R> S;
 };
+
+using BandDev = BandDevT<double>;
+using StencilDev = StencilDevT<double>;
+using LevelGeom = LevelGeomT<double>;
 
 // Tile of the level-operator kernel (i is the contiguous axis).
 constexpr int TILE_Y = 64;
@@ -90,27 +98,32 @@ struct SlotState {
 // through the scalar kernel-argument path instead of a global load).
 constexpr int ZINLINE = 32;
 
-struct ApplyArgs {
-    LevelGeom g;
+// Arguments of the level-operator kernel; R is the value type of the
+// level's vectors, bands and stencil (double, or float for the FP32
+// V-cycle).  Per-slot scalars, Chebyshev coefficients and partial sums are
+// always double.
+template <class R>
+struct ApplyArgsT {
+    LevelGeomT<R> g;
     int nslot = 0;                   // grid z: number of slots launched
     const int* slots = nullptr;      // slot of each grid z (null: identity)
     int zn = 0;                      // zn == nslot: zslot holds the list
     int zslot[ZINLINE] = {};
     const double* lam2 = nullptr;    // per slot lambda^2
     const int* active = nullptr;     // per slot, may be null (all active)
-    const double* in = nullptr;      // v, z (PUPDATE) or x (PROLONG)
-    const double* pold = nullptr;    // PRO_PUPDATE
-    double* pnew = nullptr;          // PRO_PUPDATE
+    const R* in = nullptr;           // v, z (PUPDATE) or x (PROLONG)
+    const R* pold = nullptr;         // PRO_PUPDATE
+    R* pnew = nullptr;               // PRO_PUPDATE
     const double* beta = nullptr;    // PRO_PUPDATE, per slot
-    const double* ec = nullptr;      // PRO_PROLONG coarse correction
-    double* out = nullptr;
-    const double* f = nullptr;       // right-hand side (RESID/CHEB/RESTRICT/JACOBI)
+    const R* ec = nullptr;           // PRO_PROLONG coarse correction
+    R* out = nullptr;
+    const R* f = nullptr;            // right-hand side (RESID/CHEB/RESTRICT/JACOBI)
     int f_shared = 0;                // f has one vector for all slots
-    double* d = nullptr;             // EPI_CHEB direction, in place
+    R* d = nullptr;                  // EPI_CHEB direction, in place
     const double* cheb = nullptr;    // per slot (c1, c2) of this step
     const double* cheb_first = nullptr;  // PRO_JACOBI: (c1, c2) of step 0
     int cheb_stride = 0;             // doubles between slots in cheb
-    double* fc = nullptr;            // EPI_RESTRICT coarse right-hand side
+    R* fc = nullptr;                 // EPI_RESTRICT coarse right-hand side
     int dot = 0;                     // EPI_CHEB: accumulate f . out
     double* part = nullptr;          // partial sums [slot][tile]
     int part_stride = 0;             // tiles per slot in part
@@ -120,16 +133,21 @@ struct ApplyArgs {
     const double* part_rz = nullptr; // PRO_PUPDATE: partials of r . z
     int nrz = 0;
     int parity = 0;                  // iteration parity (gam double buffer)
+    int flex = 0;                    // PRO_PUPDATE: flexible (Polak-Ribiere) beta
+    const double* part_zq = nullptr; // flex: partials of z_new . q_old
     int gate = 0;                    // convergence test before the V-cycle
     const double* part_rr = nullptr; // gate: partials of ||r||^2
     int nrr = 0;
 };
+using ApplyArgs = ApplyArgsT<double>;
 
-void launch_apply(int pro, int epi, const ApplyArgs& a, hipStream_t s);
+void launch_apply(int pro, int epi, const ApplyArgsT<double>& a, hipStream_t s);
+void launch_apply(int pro, int epi, const ApplyArgsT<float>& a, hipStream_t s);
 void configure_apply_kernels();  // LDS limits of every variant, once
 // Finest-level Chebyshev step (plain prologue): same arithmetic as
 // launch_apply(PRO_PLAIN, EPI_CHEB), distinct kernel name.
-void launch_smooth_fine(const ApplyArgs& a, hipStream_t s);
+void launch_smooth_fine(const ApplyArgsT<double>& a, hipStream_t s);
+void launch_smooth_fine(const ApplyArgsT<float>& a, hipStream_t s);
 
 // ---- setup kernels (k_setup.hip) ------------------------------------
 void launch_blur_band(const double* taps, int r, int n, int bc, double* band,
@@ -201,6 +219,17 @@ void launch_weighted_grad_sq(const double* x, const double* d, int nv, int nh,
 void launch_sub_sumsq(const double* a, const double* b, int64_t n, int nslot,
                       double* part, hipStream_t s);
 
+// FP32 V-cycle boundary (k_pcg.hip)
+void launch_to_f32(const double* src, int64_t n, int nslot, const int* slots,
+                   float* dst, hipStream_t s);
+void launch_vc_enter(SlotState* st, int* active, const int* slots, int nslot,
+                     const double* part_rr, int nrr, int64_t n, const double* r,
+                     float* r32, hipStream_t s);
+void launch_vc_exit(const int* slots, const int* active, int nslot, int64_t n,
+                    int npart, const float* z32, double* z, const double* r,
+                    const double* q, double* part_rz, double* part_zq,
+                    hipStream_t s);
+
 int apply_tiles(const LevelGeom& g);
 
 // ---- coarse tail (k_tail.hip) -----------------------------------------
@@ -215,15 +244,18 @@ struct TailLevel {
     int nu = 2;                      // smoothing steps on this level
 };
 
-struct TailArgs {
+// The tail computes in FP64; IO is the type of its right-hand side and
+// result (float under the FP32 V-cycle).
+template <class IO>
+struct TailArgsT {
     int nlev = 0;                    // tail levels, the last is the coarsest
     TailLevel lev[TAIL_MAX_LEVELS];
     int cheb_stride = 0, periodic = 0;
     const double* lam2 = nullptr;
     const int* slots = nullptr;
     const int* active = nullptr;
-    const double* f = nullptr;       // right-hand side on the first tail level
-    double* z = nullptr;             // result on the first tail level
+    const IO* f = nullptr;           // right-hand side on the first tail level
+    IO* z = nullptr;                 // result on the first tail level
     const double* W = nullptr;       // coarsest W = L^{-1} and W^T per slot
     int dot = 0;                     // write partials of f . z (level 0)
     double* part = nullptr;
@@ -235,8 +267,13 @@ struct TailArgs {
     int nrr = 0;
 };
 
-void launch_tail(const TailArgs& a, int nslot, hipStream_t s);
-size_t tail_lds_bytes(const TailArgs& a);
+using TailArgs = TailArgsT<double>;
+
+void launch_tail(const TailArgsT<double>& a, int nslot, hipStream_t s);
+void launch_tail(const TailArgsT<float>& a, int nslot, hipStream_t s);
+template <class IO>
+size_t tail_lds_bytes(const TailArgsT<IO>& a);
 size_t apply_lds_bytes(const LevelGeom& g, int epi);
+size_t apply_lds_bytes(const LevelGeomT<float>& g, int epi);
 
 }  // namespace rls

@@ -3,7 +3,8 @@
 The 512 x 512 deblurring workload (3 outer weightings x 20 lambdas in
 [1e-5, 1]) is solved on the GPU exactly as bench.py does (same smoothing
 settings, relative residual 1e-12, graph-replayed iteration chunks, each
-weighting's sweep warm-started from the previous one's solutions) and
+weighting's sweep warm-started from the previous one's solutions), in FP64
+and with the FP32 V-cycle under flexible PCG, and
 every one of the 60 solutions is compared with the oracle's x*(lambda)
 computed to the FP64 floor (DCT closed form for D = I, CG preconditioned by
 the exact D = I inverse otherwise).  Bar: relative error <= 1e-6 in x and
@@ -20,15 +21,16 @@ from tests.gpu_util import dev, host
 pytestmark = pytest.mark.gpu
 
 
-@pytest.fixture(scope="module")
-def sweeps():
+@pytest.fixture(scope="module", params=["fp64", "mixed_fp32"])
+def sweeps(request):
     import torch
     from paper_2306_11067_amd import Problem
     P_ = W.config2()
     prob = Problem(P_.nv, P_.nh, P_.taps_v, P_.taps_h, P_.bc, P_.lbc,
                    P_.levels, nu=bench.NU_FINE, cheb_ratio=bench.RATIO_FINE,
                    weights=dev(P_.weights[0]), nu_coarse=bench.NU_COARSE,
-                   cheb_ratio_coarse=bench.RATIO_COARSE)
+                   cheb_ratio_coarse=bench.RATIO_COARSE,
+                   precision=request.param)
     b = dev(P_.b)
     D = [dev(w) for w in P_.weights]
     n = P_.nv * P_.nh
@@ -43,12 +45,12 @@ def sweeps():
                                              poll_every=16)
         out.append((host(x).copy(), res, sem, info))
         x0 = x
-    return P_, out
+    return P_, out, request.param
 
 
 @pytest.mark.parametrize("ell", [0, 1, 2])
 def test_bench_workload_matches_oracle(sweeps, ell):
-    P_, out = sweeps
+    P_, out, prec = sweeps
     x, res, sem, info = out[ell]
     O = DeblurOracle(P_.nv, P_.nh, P_.taps_v, P_.taps_h, P_.bc, P_.lbc,
                      P_.weights[ell], P_.levels)
@@ -64,5 +66,5 @@ def test_bench_workload_matches_oracle(sweeps, ell):
         assert info[s]["flags"] & 1, (lam, info[s])
         assert e <= 1e-6, (ell, lam, e, info[s])
         assert er <= 1e-6 and es <= 1e-6, (ell, lam, er, es)
-    print(f"outer {ell}: worst relative error {worst:.2e}, iterations "
+    print(f"{prec} outer {ell}: worst relative error {worst:.2e}, iterations "
           f"{[i['iters'] for i in info]}")

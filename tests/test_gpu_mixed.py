@@ -1,0 +1,88 @@
+"""The FP32 V-cycle under flexible FP64 PCG (RLS_PREC_MIXED_FP32).
+
+The preconditioner runs in single precision; x, r, p, q, the dot products,
+the convergence test and the reported residual stay FP64, and the
+Polak-Ribiere beta keeps CG convergent with a preconditioner that differs
+slightly between applications.  So the bar for the solutions is the FP64
+one (relative error <= 1e-6 against the oracle's x*), while the V-cycle
+itself is compared with the oracle's FP64 V-cycle at single-precision
+accuracy: about 30 level products, each rounding at u32 = 6e-8 relative
+and amplified by at most the ~5x gain of the smoothing polynomials, give
+~1e-5; the bar is 3e-5 of the largest entry.
+"""
+import numpy as np
+import pytest
+
+import workloads as W
+from oracle.pcg import DeblurOracle
+from tests.gpu_util import dev, host
+from tests.test_gpu_steps import CASES
+from tests.test_gpu_sweep import _check_against_reference
+
+pytestmark = pytest.mark.gpu
+
+
+def _problem(P_, ell, precision):
+    from paper_2306_11067_amd import Problem
+    return Problem(P_.nv, P_.nh, P_.taps_v, P_.taps_h, P_.bc, P_.lbc,
+                   P_.levels, nu=2, cheb_ratio=4.0,
+                   weights=dev(P_.weights[ell]), precision=precision)
+
+
+@pytest.mark.parametrize("name", list(CASES))
+def test_fp32_vcycle_close_to_oracle(name):
+    from paper_2306_11067_amd import Problem
+    nv, nh, r, sg, bc, lbc, levels = CASES[name]
+    rng = np.random.default_rng(100)
+    tv = W.gaussian_taps(r, sg)
+    th = W.gaussian_taps(max(1, r - 1), sg * 0.8)
+    d = rng.uniform(0.01, 1.0, 2 * nv * nh)
+    O = DeblurOracle(nv, nh, tv, th, bc, lbc, d, levels)
+    P = Problem(nv, nh, tv, th, bc, lbc, levels, nu=2, cheb_ratio=4.0,
+                weights=dev(d), precision="mixed_fp32")
+    n = nv * nh
+    lams = np.array([1e-4, 1e-2, 1.0])
+    rr = rng.standard_normal(len(lams) * n)
+    got = host(P.vcycle(lams, dev(rr))).reshape(len(lams), n)
+    for s, lam in enumerate(lams):
+        want = O.vcycle(lam, nu=2, ratio=4.0)(rr[s * n:(s + 1) * n])
+        err = np.abs(got[s] - want).max() / np.abs(want).max()
+        assert err < 3e-5, (lam, err)
+        assert err > 0.0          # it really ran in single precision
+
+
+@pytest.mark.parametrize("ell", [0, 1])
+def test_mixed_config1_sweep_matches_oracle(ell):
+    P_ = W.config1()
+    prob = _problem(P_, ell, "mixed_fp32")
+    x, res, sem, info = prob.solve_sweep(dev(P_.b), P_.lams, 1e-12)
+    _check_against_reference(P_, ell, host(x), res, sem, info)
+
+
+def test_mixed_reflective_sweep_matches_oracle():
+    P_ = W.small_deblur(128, 96, 3, 1.5, "reflective", "neumann", 3, nlam=6,
+                        outer=1)
+    prob = _problem(P_, 1, "mixed_fp32")
+    x, res, sem, info = prob.solve_sweep(dev(P_.b), P_.lams, 1e-12)
+    _check_against_reference(P_, 1, host(x), res, sem, info)
+
+
+def test_mixed_iterations_close_to_fp64():
+    # The FP32 V-cycle may cost a few iterations (oracle measurement with an
+    # FP32-rounded V-cycle: +5 %); the bar is +15 % + 2.
+    P_ = W.config1()
+    b = dev(P_.b)
+    _, _, _, i64 = _problem(P_, 1, "fp64").solve_sweep(b, P_.lams, 1e-10)
+    _, _, _, i32 = _problem(P_, 1, "mixed_fp32").solve_sweep(b, P_.lams, 1e-10)
+    for a, m in zip(i64, i32):
+        assert m["flags"] & 1 and a["flags"] & 1
+        assert m["iters"] <= 1.15 * a["iters"] + 2, (a["iters"], m["iters"])
+
+
+def test_mixed_graph_replay_equals_direct_launches():
+    P_ = W.small_deblur(64, 64, 2, 1.0, "reflective", "neumann", 3, nlam=4)
+    prob = _problem(P_, 1, "mixed_fp32")
+    b = dev(P_.b)
+    xg = host(prob.solve_sweep(b, P_.lams, 1e-10, poll_every=4)[0])
+    xd = host(prob.solve_sweep(b, P_.lams, 1e-10, poll_every=4, graph=False)[0])
+    assert np.array_equal(xg, xd)

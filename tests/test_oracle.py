@@ -375,6 +375,45 @@ def test_cg_energy_error_monotone():
     assert all(b <= a * (1 + 1e-12) for a, b in zip(errs, errs[1:]))
 
 
+def test_flexible_cg_equals_standard_cg_for_fixed_preconditioner():
+    # With a fixed SPD preconditioner z_new . r_old = 0 in exact arithmetic,
+    # so the Polak-Ribiere beta equals the Fletcher-Reeves one and the
+    # iterates coincide (up to rounding).
+    # Moderate conditioning and few steps, before rounding-driven loss of
+    # orthogonality separates the two recurrences.
+    n = 60
+    Q, _ = np.linalg.qr(RNG.standard_normal((n, n)))
+    K = (Q * np.geomspace(1e-1, 1, n)) @ Q.T
+    G = RNG.standard_normal((n, n))
+    Minv = G @ G.T + n * np.eye(n)
+    f = RNG.standard_normal(n)
+    for m in (3, 6, 10):
+        xs, _, _, _ = pcg(lambda v: K @ v, f, lambda r: Minv @ r, tol=0.0,
+                          maxit=m)
+        xf, _, _, _ = pcg(lambda v: K @ v, f, lambda r: Minv @ r, tol=0.0,
+                          maxit=m, flexible=True)
+        assert np.linalg.norm(xf - xs) <= 1e-9 * np.linalg.norm(xs)
+
+
+def test_flexible_cg_with_varying_preconditioner_reaches_solution():
+    # A V-cycle evaluated in single precision is a slightly different map at
+    # every application; flexible CG still reaches the FP64 solution, and its
+    # iteration count stays close to that of the exact V-cycle.
+    O = _small_oracle("reflective", "neumann", nv=32, nh=32, levels=3)
+    b = RNG.standard_normal(32 * 32)
+    lam = 1e-2
+    V = O.vcycle(lam)
+    V32 = lambda r: V(r.astype(np.float32).astype(np.float64)).astype(
+        np.float32).astype(np.float64)
+    K = O.K(lam)
+    f = O.rhs(b)
+    xd = direct.solve_stacked(O.A.explicit(), O.M, b, lam)
+    x64, it64, _, _ = pcg(K, f, V, tol=1e-12)
+    x32, it32, _, _ = pcg(K, f, V32, tol=1e-12, flexible=True)
+    assert np.linalg.norm(x32 - xd) <= 1e-8 * np.linalg.norm(xd)
+    assert it32 <= 1.1 * it64
+
+
 @pytest.mark.parametrize("bc,lbc", [("reflective", "neumann"),
                                     ("periodic", "periodic")])
 def test_mg_pcg_reaches_dense_solution(bc, lbc):
