@@ -37,6 +37,7 @@ TOL = 1e-12
 NU_FINE, RATIO_FINE = 32, 400.0
 NU_COARSE, RATIO_COARSE = 2, 4.0
 HBM_PEAK_GBS = 8000.0
+COPY_PROBE_BYTES = 256 << 20    # calibration copy for the traffic counters
 
 
 def workload_config(P_):
@@ -65,6 +66,34 @@ def run_step(prob, b, D, lams, bufs):
         x0 = x
         infos.append(info)
     return infos
+
+
+def traffic_per_launch(n, launches, nbytes):
+    """HBM traffic per k_smooth_fine launch for the live launch mix, from the
+    committed FETCH_SIZE / WRITE_SIZE counters (two launch sizes, scaled by
+    a plain copy's counts), or None when the kernel's sources have changed
+    since the counters were taken."""
+    import hashlib
+    path = os.path.join(ROOT, "profiles", "k_smooth_fine_traffic.json")
+    if not os.path.exists(path) or launches == 0:
+        return None
+    with open(path) as fh:
+        J = json.load(fh)
+    h = hashlib.sha256()
+    for src in J["sources"]:
+        with open(os.path.join(ROOT, src), "rb") as fh:
+            h.update(fh.read())
+    if h.hexdigest() != J["sources_sha256"] or J["n"] != n:
+        return None
+    pts = sorted(J["points"], key=lambda p: p["slots"])
+    t = [1024.0 * (p["fetch_kib"] * J["fetch_scale"] +
+                   p["write_kib"] * J["write_scale"]) for p in pts]
+    z = [p["slots"] for p in pts]
+    slope = (t[-1] - t[0]) / (z[-1] - z[0])
+    icpt = t[0] - slope * z[0]
+    # the timer's bytes are n (40 z + 24) summed over launches
+    slot_launches = (nbytes / n - 24.0 * launches) / 40.0
+    return (icpt * launches + slope * slot_launches) / launches
 
 
 def cpu_baseline(P_, iters_per_slot, budget_s=20.0):
@@ -120,6 +149,10 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-roofline", action="store_true")
     ap.add_argument("--no-mixed", action="store_true")
+    ap.add_argument("--traffic-probe", action="store_true",
+                    help="only run the launches the HBM traffic counters are "
+                         "taken on (a copy of known size, then 4 iterations "
+                         "at 20 and at 1 lambda with direct launches)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (got --gpus {args.gpus}); the "
@@ -142,6 +175,16 @@ def main():
                    nu_coarse=NU_COARSE, cheb_ratio_coarse=RATIO_COARSE)
     bufs = [torch.empty(len(lams) * P_.nv * P_.nh, dtype=torch.float64,
                         device=dev) for _ in range(2)]
+    if args.traffic_probe:
+        src = torch.ones(COPY_PROBE_BYTES // 8, dtype=torch.float64, device=dev)
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            dst.copy_(src)
+        for lm in (lams, lams[:1]):
+            prob.solve_sweep(b, lm, 1e-30, maxit=4, poll_every=2, graph=False)
+        torch.cuda.synchronize()
+        print("traffic probe done", flush=True)
+        return
     # load every kernel once (not a step)
     prob.solve_sweep(b, lams, TOL, maxit=2, poll_every=2)
     for _ in range(args.warmup):
@@ -170,9 +213,11 @@ def main():
         prob.kernel_timer(False)
         avg_s = seconds / max(launches, 1)
         achieved = (nbytes / max(launches, 1)) / avg_s / 1e9
+        tr = traffic_per_launch(P_.nv * P_.nh, launches, nbytes)
         roof = {"bound": "hbm", "achieved": round(achieved, 1),
                 "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
+                "frac": round(achieved / HBM_PEAK_GBS, 4),
+                "traffic": None if tr is None else round(tr),
                 "kernel": "k_smooth_fine (finest-level Chebyshev step)",
                 "launches": launches,
                 "avg_launch_us": round(1e6 * avg_s, 3),
