@@ -180,6 +180,36 @@ rls_status rls_solve_sweep(rls_problem* p, const double* b, const double* lam,
                            double* seminorm, rls_solve_info* info,
                            void* stream);
 
+/* One sweep of a batch: the arguments of rls_solve_sweep for one problem,
+ * and its outcome. */
+typedef struct {
+    rls_problem* prob;          /* distinct handle per entry                 */
+    const double* b;            /* as in rls_solve_sweep                     */
+    const double* lam;
+    int nlam;
+    double tol;
+    const rls_sweep_opts* opts;
+    const double* x0;
+    double* x;
+    double* resnorm;
+    double* seminorm;
+    rls_solve_info* info;
+    rls_status status;          /* out: this sweep's status                  */
+} rls_sweep;
+
+/* Solve the sweeps of several problems of uneven sizes together (the
+ * lambda sweeps of the paper's Section 4 experiments, one per problem and
+ * outer weighting).  Each problem runs on a stream of its own, driven by a
+ * host thread of its own, so the small problems' latency-bound launches
+ * overlap on the GPU; every problem's results are bitwise those of
+ * rls_solve_sweep on it alone.  The problems' work is ordered after the
+ * work already on `stream`, and the call returns when every sweep has
+ * finished.  Returns the first failing entry's status (each entry's own
+ * status is in sweeps[i].status).
+ * Errors: RLS_E_ARG (nsweep < 1, null sweeps or handle, a handle listed
+ * twice), otherwise those of rls_solve_sweep. */
+rls_status rls_solve_batch(rls_sweep* sweeps, int nsweep, void* stream);
+
 /* Free a handle (NULL is ignored). */
 void rls_destroy(rls_problem* p);
 

@@ -194,3 +194,53 @@ class Problem:
         _check(self._lib.rls_apply_adjoint(self._h, _dptr(y, "y", nvec * self.n),
                                            _dptr(x, "x"), nvec, _stream()))
         return x
+
+
+def solve_batch(entries):
+    """Solve the lambda sweeps of several problems together (rls_solve_batch).
+
+    entries: list of dicts with keys prob, b, lams, tol and optionally x0,
+    maxit, tol_mode, poll_every, graph.  Returns a list of (x, resnorm,
+    seminorm, info) in the order of `entries`.
+    """
+    import torch
+    lib = L.load()
+    n = len(entries)
+    arr = (L.Sweep * n)()
+    keep, outs = [], []
+    for i, e in enumerate(entries):
+        prob = e["prob"]
+        lam, plam = _dbl(e["lams"])
+        nl = len(lam)
+        x = torch.empty(nl * prob.n, dtype=torch.float64, device=e["b"].device)
+        opts = L.SweepOpts(int(e.get("maxit", 100000)),
+                           L.RLS_TOL_ABSOLUTE if e.get("tol_mode") == "absolute"
+                           else L.RLS_TOL_RELATIVE,
+                           int(e.get("poll_every", 32)),
+                           1 if e.get("graph", True) else 0)
+        res = np.zeros(nl)
+        sem = np.zeros(nl)
+        info = (L.SolveInfo * nl)()
+        x0 = e.get("x0")
+        w = arr[i]
+        w.prob = prob._h
+        w.b = _dptr(e["b"], "b", prob.n)
+        w.lam = plam
+        w.nlam = nl
+        w.tol = float(e["tol"])
+        w.opts = C.pointer(opts)
+        w.x0 = None if x0 is None else _dptr(x0, "x0", nl * prob.n)
+        w.x = _dptr(x, "x", nl * prob.n)
+        w.resnorm = res.ctypes.data_as(C.POINTER(C.c_double))
+        w.seminorm = sem.ctypes.data_as(C.POINTER(C.c_double))
+        w.info = info
+        keep += [lam, opts, res, sem, info]
+        outs.append((x, res, sem, info, nl, prob.n))
+    _check(lib.rls_solve_batch(arr, n, _stream()))
+    result = []
+    for x, res, sem, info, nl, npx in outs:
+        inf = [dict(iters=i.iters, flags=i.flags, relres=i.relres,
+                    relres_true=i.relres_true) for i in info]
+        result.append((x.view(nl, npx), res, sem, inf))
+    return result
+

@@ -35,7 +35,7 @@ EXPORTS = [
     "rls_last_error", "rls_level_shape", "rls_apply_normal", "rls_vcycle",
     "rls_get_stencil", "rls_get_gram_band", "rls_gershgorin",
     "rls_apply_forward", "rls_apply_adjoint", "rls_kernel_timer",
-    "rls_kernel_timer_read",
+    "rls_kernel_timer_read", "rls_solve_batch",
 ]
 
 
@@ -68,6 +68,13 @@ _P = C.c_void_p
 _D = C.POINTER(C.c_double)
 
 
+class Sweep(C.Structure):
+    _fields_ = [("prob", _P), ("b", _P), ("lam", _D), ("nlam", C.c_int),
+                ("tol", C.c_double), ("opts", C.POINTER(SweepOpts)),
+                ("x0", _P), ("x", _P), ("resnorm", _D), ("seminorm", _D),
+                ("info", C.POINTER(SolveInfo)), ("status", C.c_int)]
+
+
 def _declare(lib):
     lib.rls_setup.argtypes = [C.POINTER(_P), C.POINTER(OpDesc),
                               C.POINTER(GridDesc), _P, _P]
@@ -90,6 +97,7 @@ def _declare(lib):
     lib.rls_apply_forward.argtypes = [_P, _P, _P, C.c_int, _P]
     lib.rls_apply_adjoint.argtypes = [_P, _P, _P, C.c_int, _P]
     lib.rls_kernel_timer.argtypes = [_P, C.c_int]
+    lib.rls_solve_batch.argtypes = [C.POINTER(Sweep), C.c_int, _P]
     lib.rls_kernel_timer_read.argtypes = [_P, C.POINTER(C.c_longlong),
                                           C.POINTER(C.c_double),
                                           C.POINTER(C.c_double)]

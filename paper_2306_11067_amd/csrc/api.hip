@@ -7,6 +7,7 @@
 #include <cstring>
 #include <memory>
 #include <string>
+#include <thread>
 #include <type_traits>
 #include <vector>
 
@@ -188,6 +189,7 @@ struct rls_problem {
     int unit_weights = 1;
     Work w;
     hipStream_t cstream = nullptr;   // capture stream for iteration graphs
+    hipStream_t bstream = nullptr;   // this problem's stream in a batch
     // Host copy of the device slot list w.slots while a sweep launches
     // iterations over it (copied into the kernel arguments when short).
     const int* hslots = nullptr;
@@ -209,6 +211,7 @@ struct rls_problem {
         for (auto* v : {&run_pool, &run_pending})
             for (auto& e : *v) { hipEventDestroy(e.a); hipEventDestroy(e.b); }
         if (cstream) hipStreamDestroy(cstream);
+        if (bstream) hipStreamDestroy(bstream);
     }
 };
 
@@ -753,6 +756,51 @@ rls_status validate_grid(const rls_grid_desc* g) {
 extern "C" {
 
 const char* rls_last_error(void) { return g_last_error.c_str(); }
+
+rls_status rls_solve_batch(rls_sweep* sweeps, int nsweep, void* stream) {
+    g_last_error.clear();
+    if (!sweeps || nsweep < 1) return fail(RLS_E_ARG, "empty batch");
+    for (int i = 0; i < nsweep; ++i) {
+        if (!sweeps[i].prob) return fail(RLS_E_ARG, "null handle in batch");
+        for (int j = 0; j < i; ++j)
+            if (sweeps[j].prob == sweeps[i].prob)
+                return fail(RLS_E_ARG, "a handle is listed twice in the batch");
+    }
+    hipStream_t s = (hipStream_t)stream;
+    // order every problem's stream after the caller's work
+    hipEvent_t ready = nullptr;
+    RLS_HIP(hipEventCreateWithFlags(&ready, hipEventDisableTiming));
+    hipError_t e = hipEventRecord(ready, s);
+    for (int i = 0; i < nsweep && e == hipSuccess; ++i) {
+        rls_problem* p = sweeps[i].prob;
+        if (!p->bstream) e = hipStreamCreateWithFlags(&p->bstream, hipStreamNonBlocking);
+        if (e == hipSuccess) e = hipStreamWaitEvent(p->bstream, ready, 0);
+    }
+    if (e != hipSuccess) {
+        (void)hipEventDestroy(ready);
+        return fail(RLS_E_HIP, std::string("batch streams: ") + hipGetErrorString(e));
+    }
+    std::vector<std::string> msgs(nsweep);
+    auto run = [&](int i) {
+        rls_sweep& w = sweeps[i];
+        (void)hipSetDevice(w.prob->device);
+        w.status = rls_solve_sweep(w.prob, w.b, w.lam, w.nlam, w.tol, w.opts,
+                                   w.x0, w.x, w.resnorm, w.seminorm, w.info,
+                                   w.prob->bstream);
+        if (w.status != RLS_OK) msgs[i] = rls_last_error();
+    };
+    std::vector<std::thread> pool;
+    pool.reserve(nsweep);
+    for (int i = 1; i < nsweep; ++i) pool.emplace_back(run, i);
+    run(0);
+    for (auto& th : pool) th.join();
+    (void)hipEventDestroy(ready);
+    // every sweep synchronized its stream before returning
+    for (int i = 0; i < nsweep; ++i)
+        if (sweeps[i].status != RLS_OK)
+            return fail(sweeps[i].status, "sweep " + std::to_string(i) + ": " + msgs[i]);
+    return RLS_OK;
+}
 
 void rls_destroy(rls_problem* p) { delete p; }
 

@@ -104,3 +104,16 @@ def test_blur_radius_beyond_lds_tile_rejected_without_gpu():
     assert lib.rls_setup(C.byref(h), C.byref(op), C.byref(g), None,
                          None) == L.RLS_E_UNSUPPORTED
     assert b"LDS" in lib.rls_last_error()
+
+
+def test_batch_argument_checks_without_gpu():
+    lib = L.load()
+    assert lib.rls_solve_batch(None, 0, None) == L.RLS_E_ARG
+    arr = (L.Sweep * 2)()
+    assert lib.rls_solve_batch(arr, 2, None) == L.RLS_E_ARG
+    assert b"null handle" in lib.rls_last_error()
+    fake = C.c_void_p(0x1000)   # never dereferenced: rejected as a duplicate
+    arr[0].prob = fake
+    arr[1].prob = fake
+    assert lib.rls_solve_batch(arr, 2, None) == L.RLS_E_ARG
+    assert b"twice" in lib.rls_last_error()
