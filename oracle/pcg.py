@@ -137,4 +137,40 @@ class DeblurOracle:
                    absolute=absolute)
 
 
-__all__ = ["pcg", "DeblurOracle", "SparseOp"]
+class CtOracle(DeblurOracle):
+    """Oracle objects for one tomography workload and outer weighting: the
+    same normal equations (paper Sec. 3.2) with a general sparse A (m x n,
+    the projector handed over by the generator) and the same one-sided
+    hierarchy A_{k+1} = A_k P (Sec. 3.2), formed here with SciPy products."""
+
+    def __init__(self, A, N, lbc, d, levels=1):
+        self.nv = self.nh = N
+        self.taps_v = self.taps_h = None
+        self.bc, self.lbc = "ct", lbc
+        self.d = np.asarray(d, dtype=np.float64)
+        self.A = SparseOp(A)
+        self.M = ops.regularizer(self.d, N, N, lbc)
+        self.levels = levels
+        self._H = None
+
+    def reference(self, b, lam, floor=1e-13, maxit=20000):
+        """x*(lambda): a dense Cholesky solve of the normal equations for
+        n <= 4096, otherwise CG preconditioned by this oracle's V-cycle run
+        to `floor` or until it stops decreasing.
+        Returns (x, relative residual of the normal equations)."""
+        import scipy.linalg as sla
+        f = self.rhs(b)
+        K = self.K(lam)
+        n = self.nv * self.nh
+        if n <= 4096:
+            A = self.A.explicit()
+            Kd = (A.T @ A).toarray() + lam * lam * (self.M.T @ self.M).toarray()
+            x = sla.cho_solve(sla.cho_factor(Kd), f)
+        else:
+            x, _, _, _ = pcg(K, f, self.vcycle(lam), tol=floor, maxit=maxit,
+                             stall=60)
+        rel = float(np.linalg.norm(f - K(x)) / np.linalg.norm(f))
+        return x, rel
+
+
+__all__ = ["pcg", "DeblurOracle", "CtOracle", "SparseOp"]
