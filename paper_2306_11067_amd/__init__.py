@@ -79,6 +79,7 @@ class Problem:
         _check(self._lib.rls_setup(C.byref(h), C.byref(op), C.byref(g), d,
                                    _stream()))
         self._h = h
+        self.m = self.n          # data values (A is square for the blur)
 
     def close(self):
         if getattr(self, "_h", None):
@@ -110,7 +111,7 @@ class Problem:
         sem = np.zeros(nl)
         info = (L.SolveInfo * nl)()
         _check(self._lib.rls_solve_sweep(
-            self._h, _dptr(b, "b", self.n), plam, nl, float(tol),
+            self._h, _dptr(b, "b", self.m), plam, nl, float(tol),
             C.byref(opts), None if x0 is None else _dptr(x0, "x0", nl * self.n),
             _dptr(x, "x", nl * self.n),
             res.ctypes.data_as(C.POINTER(C.c_double)),
@@ -183,17 +184,51 @@ class Problem:
 
     def forward(self, x, nvec=1):
         import torch
-        y = torch.empty_like(x)
+        y = torch.empty(nvec * self.m, dtype=torch.float64, device=x.device)
         _check(self._lib.rls_apply_forward(self._h, _dptr(x, "x", nvec * self.n),
                                            _dptr(y, "y"), nvec, _stream()))
         return y
 
     def adjoint(self, y, nvec=1):
         import torch
-        x = torch.empty_like(y)
-        _check(self._lib.rls_apply_adjoint(self._h, _dptr(y, "y", nvec * self.n),
+        x = torch.empty(nvec * self.n, dtype=torch.float64, device=y.device)
+        _check(self._lib.rls_apply_adjoint(self._h, _dptr(y, "y", nvec * self.m),
                                            _dptr(x, "x"), nvec, _stream()))
         return x
+
+
+class TomographyProblem(Problem):
+    """A lambda-sweep problem with a general sparse forward operator (CSR,
+    FP32 values >= 0, columns sorted within rows; e.g. the parallel-beam
+    projector of workloads.ct).  Runs with the FP32 V-cycle under flexible
+    FP64 PCG; b has m values."""
+
+    def __init__(self, rowptr, col, val, N, levels=4, nu=2, cheb_ratio=4.0,
+                 weights=None, lbc="neumann", nu_coarse=0,
+                 cheb_ratio_coarse=0.0):
+        self._lib = L.load()
+        self.nv = self.nh = int(N)
+        self.levels = int(levels)
+        self.n = self.nv * self.nh
+        self._rp = np.ascontiguousarray(rowptr, dtype=np.int64)
+        self._ci = np.ascontiguousarray(col, dtype=np.int32)
+        self._va = np.ascontiguousarray(val, dtype=np.float32)
+        self.m = len(self._rp) - 1
+        op = L.OpDesc()
+        op.kind = L.RLS_OP_CSR
+        op.m = self.m
+        op.nnz = len(self._ci)
+        op.rowptr = self._rp.ctypes.data_as(C.POINTER(C.c_int64))
+        op.col = self._ci.ctypes.data_as(C.POINTER(C.c_int32))
+        op.val = self._va.ctypes.data_as(C.POINTER(C.c_float))
+        g = L.GridDesc(self.nv, self.nh, LBC[lbc], self.levels, int(nu),
+                       float(cheb_ratio), L.RLS_PREC_MIXED_FP32, int(nu_coarse),
+                       float(cheb_ratio_coarse))
+        h = C.c_void_p()
+        d = None if weights is None else _dptr(weights, "weights", 2 * self.n)
+        _check(self._lib.rls_setup(C.byref(h), C.byref(op), C.byref(g), d,
+                                   _stream()))
+        self._h = h
 
 
 def solve_batch(entries):
@@ -224,7 +259,7 @@ def solve_batch(entries):
         x0 = e.get("x0")
         w = arr[i]
         w.prob = prob._h
-        w.b = _dptr(e["b"], "b", prob.n)
+        w.b = _dptr(e["b"], "b", prob.m)
         w.lam = plam
         w.nlam = nl
         w.tol = float(e["tol"])

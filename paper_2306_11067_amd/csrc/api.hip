@@ -103,9 +103,58 @@ struct Band {
     }
 };
 
+// Sparse A_k of a tomography level (values FP64, FP32 copies for the FP32
+// V-cycle) and pointers to the shared application workspace.
+struct CtLevel {
+    int on = 0;
+    int64_t m = 0, nnz = 0;
+    DBuf rp, ci, va, rpt, cit, vat, va32, vat32, diag, diag32, rowabs;
+    double *v = nullptr, *y = nullptr, *t = nullptr, *res = nullptr;
+    float *v32 = nullptr, *y32 = nullptr, *t32 = nullptr, *res32 = nullptr;
+    CsrDevT<double> dev() const {
+        CsrDevT<double> c;
+        if (!on) return c;
+        c.on = 1;
+        c.m = m;
+        c.rp = rp.as<int64_t>();
+        c.ci = ci.as<int>();
+        c.va = va.as<double>();
+        c.rpt = rpt.as<int64_t>();
+        c.cit = cit.as<int>();
+        c.vat = vat.as<double>();
+        c.diag = diag.as<double>();
+        c.rowabs = rowabs.as<double>();
+        c.v = v;
+        c.y = y;
+        c.t = t;
+        c.res = res;
+        return c;
+    }
+    CsrDevT<float> dev32() const {
+        CsrDevT<float> c;
+        if (!on) return c;
+        c.on = 1;
+        c.m = m;
+        c.rp = rp.as<int64_t>();
+        c.ci = ci.as<int>();
+        c.va = va32.as<float>();
+        c.rpt = rpt.as<int64_t>();
+        c.cit = cit.as<int>();
+        c.vat = vat32.as<float>();
+        c.diag = diag32.as<float>();
+        c.rowabs = rowabs.as<double>();
+        c.v = v32;
+        c.y = y32;
+        c.t = t32;
+        c.res = res32;
+        return c;
+    }
+};
+
 struct Level {
     int nv = 0, nh = 0;
     Band gv, gh;
+    CtLevel ct;
     DBuf planes, srowabs;
     int nine = 0;
     int periodic = 0;
@@ -127,6 +176,7 @@ struct Level {
         g.S.rowabs = srowabs.as<double>();
         g.S.nine = nine;
         g.S.periodic = periodic;
+        g.ct = ct.dev();
         return g;
     }
     LevelGeomT<float> geom32() const {
@@ -144,6 +194,7 @@ struct Level {
         g.S.cse = pl + 4 * m;
         g.S.nine = nine;
         g.S.periodic = periodic;
+        g.ct = ct.dev32();
         return g;
     }
     template <class R> LevelGeomT<R> geom_t() const;
@@ -160,6 +211,7 @@ struct Work {
     DBuf part_pq, part_rr, part_rz;    // PCG partial sums per slot
     DBuf part_zq;                      // flexible beta: partials of z . q
     DBuf r32, z32;                     // FP32 V-cycle: fine rhs and result
+    DBuf ctv, cty, ctt, ctres, ctv32, cty32, ctt32, ctres32;  // sparse levels
     std::vector<DBuf> lx32, lxb32, ld32, lf32;   // FP32 level vectors
     int* h_active = nullptr;     // pinned host mirrors
     int* h_slots = nullptr;
@@ -177,6 +229,9 @@ struct rls_problem {
     int device = 0;
     int nv = 0, nh = 0, levels = 0, bc = 0, lbc = 0;
     int prec = RLS_PREC_FP64;    // V-cycle arithmetic
+    int is_ct = 0;               // sparse (tomography) forward operator
+    int64_t ct_m = 0;            // its rows
+    DBuf ct_gram;                // dense A_c^T A_c of the coarsest level
     std::vector<int> nu;         // Chebyshev steps per level
     std::vector<double> ratio;   // Chebyshev interval ratio per level
     int nu_max = 2;
@@ -219,6 +274,7 @@ namespace {
 
 int max_part_slots(const rls_problem* P) {
     int m = vec_blocks(P->n());
+    if (P->is_ct) m = std::max(m, vec_blocks(P->ct_m));
     for (const Level& L : P->lev) m = std::max(m, apply_tiles(L.geom()));
     return m;
 }
@@ -249,13 +305,25 @@ void run_begin(rls_problem* P, hipStream_t s) {
     hipEventRecord(P->run_cur.a, s);
 }
 
+// The level operator of either operator kind.
+template <class R>
+void level_apply(int pro, int epi, const ApplyArgsT<R>& a, hipStream_t s) {
+    if (a.g.ct.on) launch_ct_apply(pro, epi, a, s);
+    else launch_apply(pro, epi, a, s);
+}
+
 void smooth_fine(rls_problem* P, const ApplyArgs& a, hipStream_t s) {
+    if (a.g.ct.on) {
+        launch_ct_apply(PRO_PLAIN, EPI_CHEB, a, s);
+        return;
+    }
     launch_smooth_fine(a, s);
     if (P->timer_on) P->run_cur.launches += 1;
 }
 // FP32 V-cycle: not timed (the kernel timer covers the FP64 step).
 void smooth_fine(rls_problem*, const ApplyArgsT<float>& a, hipStream_t s) {
-    launch_smooth_fine(a, s);
+    if (a.g.ct.on) launch_ct_apply(PRO_PLAIN, EPI_CHEB, a, s);
+    else launch_smooth_fine(a, s);
 }
 
 void run_end(rls_problem* P, hipStream_t s) {
@@ -330,6 +398,27 @@ rls_status ensure_work(rls_problem* P, int nslot) {
         if (k > 0) {
             RLS_TRY(dalloc(w.lx[k], bytes));
             RLS_TRY(dalloc(w.lf[k], bytes));
+        }
+    }
+    if (P->is_ct) {
+        const size_t cn = (size_t)cap * n, cm = (size_t)cap * P->ct_m;
+        RLS_TRY(dalloc(w.ctv, sizeof(double) * cn));
+        RLS_TRY(dalloc(w.cty, sizeof(double) * cm));
+        RLS_TRY(dalloc(w.ctt, sizeof(double) * cn));
+        RLS_TRY(dalloc(w.ctres, sizeof(double) * cn));
+        RLS_TRY(dalloc(w.ctv32, sizeof(float) * cn));
+        RLS_TRY(dalloc(w.cty32, sizeof(float) * cm));
+        RLS_TRY(dalloc(w.ctt32, sizeof(float) * cn));
+        RLS_TRY(dalloc(w.ctres32, sizeof(float) * cn));
+        for (Level& Lv : P->lev) {
+            Lv.ct.v = w.ctv.as<double>();
+            Lv.ct.y = w.cty.as<double>();
+            Lv.ct.t = w.ctt.as<double>();
+            Lv.ct.res = w.ctres.as<double>();
+            Lv.ct.v32 = w.ctv32.as<float>();
+            Lv.ct.y32 = w.cty32.as<float>();
+            Lv.ct.t32 = w.ctt32.as<float>();
+            Lv.ct.res32 = w.ctres32.as<float>();
         }
     }
     if (P->prec == RLS_PREC_MIXED_FP32) {
@@ -440,6 +529,114 @@ rls_status build_direction(rls_problem* P, const std::vector<double>& taps,
     return RLS_OK;
 }
 
+// Sparse operator hierarchy (paper Section 3.2, one-sided): A_0 = A, then
+// A_{k+1} = A_k P row by row, A_k^T by a deterministic transpose, column
+// statistics diag(A_k^T A_k) and A_k^T A_k 1, and the dense A_c^T A_c of
+// the coarsest level.  All on the GPU; the host only reads the sizes.
+rls_status build_ct(rls_problem* P, const rls_op_desc* A, hipStream_t s) {
+    const int64_t m = A->m;
+    DBuf err;
+    RLS_TRY(dalloc(err, sizeof(int)));
+    RLS_HIP(hipMemsetAsync(err.p, 0, sizeof(int), s));
+    {
+        CtLevel& c = P->lev[0].ct;
+        c.on = 1;
+        c.m = m;
+        c.nnz = A->nnz;
+        RLS_TRY(dalloc(c.rp, sizeof(int64_t) * (m + 1)));
+        RLS_TRY(dalloc(c.ci, sizeof(int) * c.nnz));
+        RLS_TRY(dalloc(c.va, sizeof(double) * c.nnz));
+        RLS_TRY(dalloc(c.va32, sizeof(float) * c.nnz));
+        RLS_HIP(hipMemcpyAsync(c.rp.p, A->rowptr, sizeof(int64_t) * (m + 1),
+                               hipMemcpyHostToDevice, s));
+        RLS_HIP(hipMemcpyAsync(c.ci.p, A->col, sizeof(int) * c.nnz,
+                               hipMemcpyHostToDevice, s));
+        RLS_HIP(hipMemcpyAsync(c.va32.p, A->val, sizeof(float) * c.nnz,
+                               hipMemcpyHostToDevice, s));
+        launch_f64_from_f32(c.va32.as<float>(), c.nnz, c.va.as<double>(), s);
+    }
+    DBuf cnt, ones_y;
+    RLS_TRY(dalloc(cnt, sizeof(int64_t) * (std::max<int64_t>(m, P->n()) + 1)));
+    RLS_TRY(dalloc(ones_y, sizeof(double) * m));
+    for (int k = 0; k < P->levels; ++k) {
+        Level& Lk = P->lev[k];
+        CtLevel& c = Lk.ct;
+        const int64_t nk = Lk.n();
+        if (k > 0) {
+            const Level& Lf = P->lev[k - 1];
+            const CtLevel& f = Lf.ct;
+            c.on = 1;
+            c.m = m;
+            RLS_TRY(dalloc(c.rp, sizeof(int64_t) * (m + 1)));
+            launch_csr_coarsen(f.rp.as<int64_t>(), f.ci.as<int>(),
+                               f.va.as<double>(), m, Lf.nv, Lf.nh, P->periodic,
+                               0, cnt.as<int64_t>(), nullptr, nullptr, nullptr,
+                               err.as<int>(), s);
+            launch_scan_excl(cnt.as<int64_t>(), m, c.rp.as<int64_t>(), s);
+            int64_t nnz = 0;
+            RLS_HIP(hipMemcpyAsync(&nnz, c.rp.as<int64_t>() + m, sizeof(int64_t),
+                                   hipMemcpyDeviceToHost, s));
+            RLS_HIP(hipStreamSynchronize(s));
+            c.nnz = nnz;
+            RLS_TRY(dalloc(c.ci, sizeof(int) * std::max<int64_t>(nnz, 1)));
+            RLS_TRY(dalloc(c.va, sizeof(double) * std::max<int64_t>(nnz, 1)));
+            launch_csr_coarsen(f.rp.as<int64_t>(), f.ci.as<int>(),
+                               f.va.as<double>(), m, Lf.nv, Lf.nh, P->periodic,
+                               1, nullptr, c.rp.as<int64_t>(), c.ci.as<int>(),
+                               c.va.as<double>(), err.as<int>(), s);
+            RLS_TRY(dalloc(c.va32, sizeof(float) * std::max<int64_t>(nnz, 1)));
+            launch_to_f32(c.va.as<double>(), nnz, 1, nullptr, c.va32.as<float>(), s);
+        }
+        // transpose
+        RLS_TRY(dalloc(c.rpt, sizeof(int64_t) * (nk + 1)));
+        RLS_TRY(dalloc(c.cit, sizeof(int) * std::max<int64_t>(c.nnz, 1)));
+        RLS_TRY(dalloc(c.vat, sizeof(double) * std::max<int64_t>(c.nnz, 1)));
+        RLS_HIP(hipMemsetAsync(cnt.p, 0, sizeof(int64_t) * (nk + 1), s));
+        launch_csr_transpose_count(c.ci.as<int>(), c.nnz,
+                                   cnt.as<unsigned long long>(), s);
+        launch_scan_excl(cnt.as<int64_t>(), nk, c.rpt.as<int64_t>(), s);
+        RLS_HIP(hipMemsetAsync(cnt.p, 0, sizeof(int64_t) * (nk + 1), s));
+        launch_csr_transpose_fill(c.rp.as<int64_t>(), c.ci.as<int>(),
+                                  c.va.as<double>(), m, nk, c.rpt.as<int64_t>(),
+                                  cnt.as<unsigned long long>(), c.cit.as<int>(),
+                                  c.vat.as<double>(), err.as<int>(), s);
+        RLS_TRY(dalloc(c.vat32, sizeof(float) * std::max<int64_t>(c.nnz, 1)));
+        launch_to_f32(c.vat.as<double>(), c.nnz, 1, nullptr, c.vat32.as<float>(), s);
+        // diag(A_k^T A_k) and A_k^T (A_k 1)
+        RLS_TRY(dalloc(c.diag, sizeof(double) * nk));
+        RLS_TRY(dalloc(c.diag32, sizeof(float) * nk));
+        RLS_TRY(dalloc(c.rowabs, sizeof(double) * nk));
+        launch_row_sumsq(c.rpt.as<int64_t>(), c.vat.as<double>(), nk,
+                         c.diag.as<double>(), s);
+        launch_to_f32(c.diag.as<double>(), nk, 1, nullptr, c.diag32.as<float>(), s);
+        launch_spmv<double, double, double>(c.rp.as<int64_t>(), c.ci.as<int>(),
+                                            c.va.as<double>(), m, nk, nullptr, 1,
+                                            m, ones_y.as<double>(), 1, nullptr,
+                                            nullptr, s);
+        launch_spmv<double, double, double>(c.rpt.as<int64_t>(), c.cit.as<int>(),
+                                            c.vat.as<double>(), nk, m,
+                                            ones_y.as<double>(), 1, nk,
+                                            c.rowabs.as<double>(), 1, nullptr,
+                                            nullptr, s);
+    }
+    {
+        const Level& C = P->lev[P->levels - 1];
+        const int nc = (int)C.n();
+        RLS_TRY(dalloc(P->ct_gram, sizeof(double) * (size_t)nc * nc));
+        launch_dense_gram(C.ct.rpt.as<int64_t>(), C.ct.cit.as<int>(),
+                          C.ct.vat.as<double>(), nc, P->ct_gram.as<double>(), s);
+    }
+    RLS_TRY(check_launch("build_ct"));
+    int herr = 0;
+    RLS_HIP(hipMemcpyAsync(&herr, err.p, sizeof(int), hipMemcpyDeviceToHost, s));
+    RLS_HIP(hipStreamSynchronize(s));
+    if (herr)
+        return fail(RLS_E_UNSUPPORTED,
+                    "sparse operator rows or columns too long for the on-GPU "
+                    "hierarchy build (row: 512 nonzeros, column: 4096)");
+    return RLS_OK;
+}
+
 rls_status install_weights(rls_problem* P, const double* d, hipStream_t s) {
     const int64_t n = P->n();
     if (d) {
@@ -516,14 +713,24 @@ rls_status prepare_sweep(rls_problem* P, int nslot, hipStream_t s) {
     const int cs = 2 * P->nu_max;
     for (int k = 0; k + 1 < L; ++k) {
         double* rho = w.rho.as<double>() + (size_t)k * w.cap;
-        launch_gershgorin(P->lev[k].geom(), w.lam2.as<double>(), nslot, rho, s);
+        if (P->is_ct)
+            launch_gershgorin_ct(P->lev[k].geom(), w.lam2.as<double>(), nslot,
+                                 rho, s);
+        else
+            launch_gershgorin(P->lev[k].geom(), w.lam2.as<double>(), nslot,
+                              rho, s);
         launch_cheb_coeffs(rho, nslot, P->ratio[k], P->nu[k], cs,
                            w.cheb.as<double>() + (size_t)k * w.cap * cs, s);
     }
     const Level& C = P->lev[L - 1];
     const int nc = (int)C.n();
-    launch_coarse_assemble(C.geom(), w.lam2.as<double>(), nslot,
-                           w.kc.as<double>(), s);
+    if (P->is_ct)
+        launch_coarse_assemble_ct(C.geom(), P->ct_gram.as<double>(),
+                                  w.lam2.as<double>(), nslot,
+                                  w.kc.as<double>(), s);
+    else
+        launch_coarse_assemble(C.geom(), w.lam2.as<double>(), nslot,
+                               w.kc.as<double>(), s);
     launch_cholesky_inverse(w.kc.as<double>(), nc, nslot, w.winv.as<double>(),
                             w.info.as<int>(), s);
     RLS_TRY(check_launch("prepare_sweep"));
@@ -655,7 +862,7 @@ void vcycle(rls_problem* P, int k, int nslot, const int* slots,
         ApplyArgsT<R> r = a;
         gate_first(r);
         r.fc = fc;
-        launch_apply(PRO_JACOBI, EPI_RESTRICT, r, s);
+        level_apply(PRO_JACOBI, EPI_RESTRICT, r, s);
         vcycle(P, k + 1, nslot, slots, active, (const R*)fc, zc, CycleCtl(), s);
         ApplyArgsT<R> c = a;
         c.ec = zc;
@@ -666,7 +873,7 @@ void vcycle(rls_problem* P, int k, int nslot, const int* slots,
             c.part = ctl.dot_part;
             c.part_stride = ctl.dot_stride;
         }
-        launch_apply(PRO_PROLONG_JAC, EPI_CHEB, c, s);
+        level_apply(PRO_PROLONG_JAC, EPI_CHEB, c, s);
         return;
     }
     // nu >= 2.  Buffer writes: the first pre-smoothing step writes buffer 0,
@@ -682,7 +889,7 @@ void vcycle(rls_problem* P, int k, int nslot, const int* slots,
         gate_first(j);
         j.out = bufs[cur];
         j.cheb = cheb + 2;
-        launch_apply(PRO_JACOBI, EPI_CHEB, j, s);   // x1 = c f / diag, step 2
+        level_apply(PRO_JACOBI, EPI_CHEB, j, s);   // x1 = c f / diag, step 2
     }
     if (TIMED && top && nu > 2) run_begin(P, s);
     for (int st = 2; st < nu; ++st) {
@@ -691,7 +898,7 @@ void vcycle(rls_problem* P, int k, int nslot, const int* slots,
         c.out = bufs[1 - cur];
         c.cheb = cheb + 2 * st;
         if (top) smooth_fine(P, c, s);
-        else launch_apply(PRO_PLAIN, EPI_CHEB, c, s);
+        else level_apply(PRO_PLAIN, EPI_CHEB, c, s);
         cur = 1 - cur;
     }
     if (TIMED && top && nu > 2) run_end(P, s);
@@ -699,7 +906,7 @@ void vcycle(rls_problem* P, int k, int nslot, const int* slots,
         ApplyArgsT<R> r = a;                        // residual + restriction
         r.in = bufs[cur];
         r.fc = fc;
-        launch_apply(PRO_PLAIN, EPI_RESTRICT, r, s);
+        level_apply(PRO_PLAIN, EPI_RESTRICT, r, s);
     }
     vcycle(P, k + 1, nslot, slots, active, (const R*)fc, zc, CycleCtl(), s);
     for (int st = 0; st < nu; ++st) {              // correction + smoothing
@@ -715,7 +922,7 @@ void vcycle(rls_problem* P, int k, int nslot, const int* slots,
         }
         if (TIMED && top && st == 1) run_begin(P, s);
         if (top && st > 0) smooth_fine(P, c, s);
-        else launch_apply(st == 0 ? PRO_PROLONG : PRO_PLAIN, EPI_CHEB, c, s);
+        else level_apply(st == 0 ? PRO_PROLONG : PRO_PLAIN, EPI_CHEB, c, s);
         if (TIMED && top && st > 0 && st == nu - 1) run_end(P, s);
         cur = 1 - cur;
     }
@@ -804,14 +1011,78 @@ rls_status rls_solve_batch(rls_sweep* sweeps, int nsweep, void* stream) {
 
 void rls_destroy(rls_problem* p) { delete p; }
 
+// rls_setup for a sparse (tomography) operator.
+static rls_status setup_ct(rls_problem** out, const rls_op_desc* A,
+                           const rls_grid_desc* g, const double* d,
+                           void* stream) {
+    if (g->precision != RLS_PREC_MIXED_FP32)
+        return fail(RLS_E_UNSUPPORTED,
+                    "sparse operators run with RLS_PREC_MIXED_FP32 (FP32 "
+                    "V-cycle, FP64 PCG)");
+    const int64_t n = (int64_t)g->nv * g->nh;
+    if (n > (int64_t)1 << 28)
+        return fail(RLS_E_UNSUPPORTED, "grids are limited to 2^28 points");
+    if (A->m < 1 || A->nnz < 1 || !A->rowptr || !A->col || !A->val)
+        return fail(RLS_E_ARG, "sparse operator: m, nnz >= 1 and host rowptr, "
+                               "col, val required");
+    if (A->rowptr[0] != 0 || A->rowptr[A->m] != A->nnz)
+        return fail(RLS_E_ARG, "rowptr must start at 0 and end at nnz");
+    for (int64_t i = 0; i < A->m; ++i) {
+        if (A->rowptr[i + 1] < A->rowptr[i])
+            return fail(RLS_E_ARG, "rowptr must be nondecreasing");
+        if (A->rowptr[i + 1] - A->rowptr[i] > 512)
+            return fail(RLS_E_UNSUPPORTED, "rows are limited to 512 nonzeros");
+        for (int64_t e = A->rowptr[i]; e < A->rowptr[i + 1]; ++e) {
+            if (A->col[e] < 0 || A->col[e] >= n ||
+                (e > A->rowptr[i] && A->col[e] <= A->col[e - 1]))
+                return fail(RLS_E_ARG, "columns must be in [0, nv*nh) and "
+                                       "strictly increasing within a row");
+            if (!(A->val[e] >= 0.0f) || !std::isfinite(A->val[e]))
+                return fail(RLS_E_ARG, "values must be finite and >= 0 (ray "
+                                       "lengths)");
+        }
+    }
+    std::unique_ptr<rls_problem> P(new rls_problem());
+    RLS_HIP(hipGetDevice(&P->device));
+    RLS_HIP(hipStreamCreateWithFlags(&P->cstream, hipStreamNonBlocking));
+    configure_apply_kernels();
+    P->nv = g->nv;
+    P->nh = g->nh;
+    P->levels = g->levels;
+    P->prec = g->precision;
+    P->is_ct = 1;
+    P->ct_m = A->m;
+    for (int k = 0; k < g->levels; ++k) {
+        const bool fine = k == 0;
+        P->nu.push_back(fine || g->nu_coarse == 0 ? g->nu : g->nu_coarse);
+        P->ratio.push_back(fine || g->cheb_ratio_coarse == 0.0
+                               ? g->cheb_ratio : g->cheb_ratio_coarse);
+    }
+    P->nu_max = *std::max_element(P->nu.begin(), P->nu.end());
+    P->bc = -1;
+    P->lbc = g->lbc;
+    P->periodic = g->lbc == RLS_L_PERIODIC;
+    P->lev.resize(P->levels);
+    for (int k = 0; k < P->levels; ++k) {
+        P->lev[k].nv = P->nv >> k;
+        P->lev[k].nh = P->nh >> k;
+    }
+    P->kt = P->levels - 1;    // the tail kernel solves the coarsest level only
+    hipStream_t s = (hipStream_t)stream;
+    RLS_TRY(build_ct(P.get(), A, s));
+    RLS_TRY(install_weights(P.get(), d, s));
+    RLS_HIP(hipStreamSynchronize(s));
+    *out = P.release();
+    return RLS_OK;
+}
+
 rls_status rls_setup(rls_problem** out, const rls_op_desc* A,
                      const rls_grid_desc* g, const double* d, void* stream) {
     g_last_error.clear();
     if (!out || !A || !g) return fail(RLS_E_ARG, "null argument");
     *out = nullptr;
     RLS_TRY(validate_grid(g));
-    if (A->kind == RLS_OP_CSR)
-        return fail(RLS_E_UNSUPPORTED, "sparse operators are not supported yet");
+    if (A->kind == RLS_OP_CSR) return setup_ct(out, A, g, d, stream);
     if (A->kind != RLS_OP_BLUR_SEPARABLE) return fail(RLS_E_ARG, "unknown operator kind");
     if (!A->taps_v || !A->taps_h) return fail(RLS_E_ARG, "null taps");
     if (A->r_v < 0 || A->r_h < 0 || 2 * A->r_v + 1 > g->nv || 2 * A->r_h + 1 > g->nh)
@@ -914,6 +1185,8 @@ rls_status rls_get_stencil(const rls_problem* p, int level, double* out) {
 
 rls_status rls_get_gram_band(const rls_problem* p, int level, int dir, int* bw,
                              double* out) {
+    if (p && p->is_ct)
+        return fail(RLS_E_UNSUPPORTED, "sparse operators have no Gram bands");
     if (!p) return fail(RLS_E_STATE, "null handle");
     if (level < 0 || level >= p->levels || dir < 0 || dir > 1)
         return fail(RLS_E_ARG, "bad level/direction");
@@ -941,7 +1214,7 @@ rls_status rls_apply_normal(rls_problem* p, int level, const double* lam,
     a.lam2 = p->w.lam2.as<double>();
     a.in = v;
     a.out = out;
-    launch_apply(PRO_PLAIN, EPI_STORE, a, s);
+    level_apply(PRO_PLAIN, EPI_STORE, a, s);
     RLS_TRY(check_launch("rls_apply_normal"));
     RLS_HIP(hipStreamSynchronize(s));
     return RLS_OK;
@@ -956,8 +1229,12 @@ rls_status rls_gershgorin(rls_problem* p, int level, const double* lam,
     hipStream_t s = (hipStream_t)stream;
     RLS_TRY(ensure_work(p, nlam));
     RLS_TRY(upload_lam(p, lam, nlam, s));
-    launch_gershgorin(p->lev[level].geom(), p->w.lam2.as<double>(), nlam,
-                      p->w.rho.as<double>(), s);
+    if (p->is_ct)
+        launch_gershgorin_ct(p->lev[level].geom(), p->w.lam2.as<double>(), nlam,
+                             p->w.rho.as<double>(), s);
+    else
+        launch_gershgorin(p->lev[level].geom(), p->w.lam2.as<double>(), nlam,
+                          p->w.rho.as<double>(), s);
     RLS_TRY(check_launch("rls_gershgorin"));
     RLS_HIP(hipMemcpyAsync(rho, p->w.rho.p, sizeof(double) * nlam,
                            hipMemcpyDeviceToHost, s));
@@ -1011,6 +1288,20 @@ rls_status rls_kernel_timer_read(const rls_problem* p, long long* launches,
 static rls_status apply_blur(rls_problem* p, int transpose, const double* x,
                              double* y, int nvec, hipStream_t s) {
     RLS_TRY(ensure_work(p, nvec));
+    if (p->is_ct) {
+        // y = A x (n -> m) or y = A^T x (m -> n), FP64
+        const CtLevel& c = p->lev[0].ct;
+        const int64_t n = p->n(), m = p->ct_m;
+        if (!transpose)
+            launch_spmv<double, double, double>(
+                c.rp.as<int64_t>(), c.ci.as<int>(), c.va.as<double>(), m, n,
+                x, 0, m, y, nvec, nullptr, nullptr, s);
+        else
+            launch_spmv<double, double, double>(
+                c.rpt.as<int64_t>(), c.cit.as<int>(), c.vat.as<double>(), n, m,
+                x, 0, n, y, nvec, nullptr, nullptr, s);
+        return check_launch("apply_operator");
+    }
     ApplyArgs a;
     a.g = blur_geom(p, transpose);
     a.nslot = nvec;
@@ -1093,7 +1384,7 @@ rls_status rls_solve_sweep(rls_problem* p, const double* b, const double* lam,
         a.out = r;
         a.f = f;
         a.f_shared = 1;
-        launch_apply(PRO_PLAIN, EPI_RESID, a, s);
+        level_apply(PRO_PLAIN, EPI_RESID, a, s);
     } else {
         RLS_HIP(hipMemsetAsync(x, 0, sizeof(double) * ns * n, s));
         launch_broadcast(f, n, ns, r, s);
@@ -1148,7 +1439,7 @@ rls_status rls_solve_sweep(rls_problem* p, const double* b, const double* lam,
             ak.flex = 1;
             ak.part_zq = w.part_zq.as<double>();
         }
-        launch_apply(PRO_PUPDATE, EPI_DOT, ak, ss);
+        level_apply(PRO_PUPDATE, EPI_DOT, ak, ss);
         launch_update_xr(st, active, sl, n, nact, x, r, pb[1 - cur], q,
                          w.part_pq.as<double>(), tiles0, cur,
                          w.part_rr.as<double>(), ss);
@@ -1245,15 +1536,20 @@ rls_status rls_solve_sweep(rls_problem* p, const double* b, const double* lam,
     a.out = q;
     a.f = f;
     a.f_shared = 1;
-    launch_apply(PRO_PLAIN, EPI_RESID, a, s);
+    level_apply(PRO_PLAIN, EPI_RESID, a, s);
     double* o_true = w.outv.as<double>();
     double* o_res = o_true + ns;
     double* o_sem = o_true + 2 * ns;
     launch_sumsq_slots(q, n, ns, part, s);
     launch_reduce_slots(part, vb, ns, o_true, s);
-    RLS_TRY(apply_blur(p, 0, x, w.y.as<double>(), ns, s));
-    launch_sub_sumsq(w.y.as<double>(), b, n, ns, part, s);
-    launch_reduce_slots(part, vb, ns, o_res, s);
+    {
+        // ||A x - b|| over the data space (m values for a sparse operator)
+        const int64_t md = p->is_ct ? p->ct_m : n;
+        double* ax = p->is_ct ? w.cty.as<double>() : w.y.as<double>();
+        RLS_TRY(apply_blur(p, 0, x, ax, ns, s));
+        launch_sub_sumsq(ax, b, md, ns, part, s);
+        launch_reduce_slots(part, vec_blocks(md), ns, o_res, s);
+    }
     launch_weighted_grad_sq(x, p->unit_weights ? nullptr : p->weights.as<double>(),
                             p->nv, p->nh, p->periodic, ns, part, s);
     launch_reduce_slots(part, vb, ns, o_sem, s);

@@ -683,7 +683,10 @@ void configure_apply_kernels() {
     done = true;
 }
 
+// Partial sums per slot of a level's kernels: one per tile, or one per
+// workgroup of the sparse-level kernels.
 int apply_tiles(const LevelGeom& g) {
+    if (g.ct.on) return ct_parts((int64_t)g.nv * g.nh);
     return ((g.nv + TILE_Y - 1) / TILE_Y) * ((g.nh + TILE_X - 1) / TILE_X);
 }
 

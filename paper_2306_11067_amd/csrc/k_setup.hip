@@ -321,6 +321,51 @@ __global__ void k_coarse_assemble(LevelGeom g, const double* __restrict__ lam2,
         }
 }
 
+// Gershgorin bound for a sparse level: rho = max_p (|A^T A| 1 + lam^2
+// |S| 1)_p / K_pp, with A >= 0 so |A^T A| 1 = A^T (A 1).
+__global__ void __launch_bounds__(256)
+k_gershgorin_ct(LevelGeom g, const double* __restrict__ lam2,
+                double* __restrict__ rho) {
+    __shared__ double sh[256];
+    const int slot = blockIdx.x;
+    const double l2 = lam2[slot];
+    const int64_t n = (int64_t)g.nv * g.nh;
+    double m = 0.0;
+    for (int64_t p = threadIdx.x; p < n; p += 256) {
+        const double num = g.ct.rowabs[p] + l2 * g.S.rowabs[p];
+        const double den = g.ct.diag[p] + l2 * g.S.c[p];
+        m = fmax(m, num / den);
+    }
+    m = block_max<256>(m, sh);
+    if (threadIdx.x == 0) rho[slot] = m;
+}
+
+// Dense coarsest operator A_c^T A_c + lam^2 S for a sparse level (the Gram
+// G is lambda-free and formed once), column-major, per slot.
+__global__ void k_coarse_assemble_ct(LevelGeom g, const double* __restrict__ G,
+                                     const double* __restrict__ lam2,
+                                     double* __restrict__ Kc) {
+    const int n = g.nv * g.nh;
+    const int slot = blockIdx.y;
+    const int col = blockIdx.x * blockDim.x + threadIdx.x;
+    if (col >= n) return;
+    const double l2 = lam2[slot];
+    double* K = Kc + (size_t)slot * n * n + (size_t)col * n;
+    for (int r = 0; r < n; ++r) K[r] = G[(size_t)col * n + r];
+    const int i = col % g.nv, j = col / g.nv;
+    const int periodic = g.S.periodic;
+    for (int di = -1; di <= 1; ++di)
+        for (int dj = -1; dj <= 1; ++dj) {
+            const double s = stencil_entry(g.S.c, g.nv, g.nh, periodic, i, j,
+                                           di, dj);
+            if (s == 0.0) continue;
+            int ii = i + di, jj = j + dj;
+            wrap_or_drop(ii, g.nv, periodic);
+            wrap_or_drop(jj, g.nh, periodic);
+            K[ii + g.nv * jj] += l2 * s;
+        }
+}
+
 // Cholesky K = L L^T (in place, lower, column-major) and W = L^{-1}
 // (row-major into `work`, transposed copy after it).  One block per slot.
 // info[slot] = 0, or the 1-based index of the first non-positive pivot.
@@ -445,6 +490,18 @@ void launch_coarse_assemble(const LevelGeom& g, const double* lam2, int nslot,
     const int n = g.nv * g.nh;
     hipLaunchKernelGGL(k_coarse_assemble, dim3(nblk(n, 128), nslot), dim3(128),
                        0, s, g, lam2, Kc);
+}
+void launch_gershgorin_ct(const LevelGeom& g, const double* lam2, int nslot,
+                          double* rho, hipStream_t s) {
+    hipLaunchKernelGGL(k_gershgorin_ct, dim3(nslot), dim3(256), 0, s, g, lam2,
+                       rho);
+}
+void launch_coarse_assemble_ct(const LevelGeom& g, const double* G,
+                               const double* lam2, int nslot, double* Kc,
+                               hipStream_t s) {
+    const int n = g.nv * g.nh;
+    hipLaunchKernelGGL(k_coarse_assemble_ct, dim3(nblk(n, 128), nslot),
+                       dim3(128), 0, s, g, G, lam2, Kc);
 }
 void launch_cholesky_inverse(double* Kc, int n, int nslot, double* work,
                              int* info, hipStream_t s) {

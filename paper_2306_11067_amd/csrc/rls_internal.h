@@ -45,11 +45,33 @@ struct StencilDevT {
     int periodic = 0;
 };
 
+// A level whose A_k^T A_k is applied through a sparse A_k (tomography):
+// A_k (m x n_k) and A_k^T as CSR, column statistics, and the workspace of
+// one application (shared by all levels, sized for the finest).
+template <class R>
+struct CsrDevT {
+    int on = 0;
+    int64_t m = 0;
+    const int64_t* rp = nullptr;    // A_k
+    const int* ci = nullptr;
+    const R* va = nullptr;
+    const int64_t* rpt = nullptr;   // A_k^T
+    const int* cit = nullptr;
+    const R* vat = nullptr;
+    const R* diag = nullptr;        // diag(A_k^T A_k)
+    const double* rowabs = nullptr; // A_k^T A_k 1 (A_k >= 0 entrywise)
+    R* v = nullptr;                 // [slot][n_k] operand after the prologue
+    R* y = nullptr;                 // [slot][m]   A_k v
+    R* t = nullptr;                 // [slot][n_k] A_k^T y
+    R* res = nullptr;               // [slot][n_k] residual before restriction
+};
+
 template <class R>
 struct LevelGeomT {
     int nv = 0, nh = 0;
     BandDevT<R> gv, gh;         // separable Gram G_h (x) G_v
     StencilDevT<R> S;
+    CsrDevT<R> ct;              // sparse A_k instead of the bands (ct.on)
 };
 
 using BandDev = BandDevT<double>;
@@ -218,6 +240,40 @@ void launch_weighted_grad_sq(const double* x, const double* d, int nv, int nh,
                              hipStream_t s);
 void launch_sub_sumsq(const double* a, const double* b, int64_t n, int nslot,
                       double* part, hipStream_t s);
+
+// ---- sparse operators (k_csr.hip, k_ct.hip) ------------------------------
+void launch_scan_excl(const int64_t* cnt, int64_t n, int64_t* out,
+                      hipStream_t s);
+void launch_csr_transpose_count(const int* ci, int64_t nnz,
+                                unsigned long long* cnt, hipStream_t s);
+void launch_csr_transpose_fill(const int64_t* rp, const int* ci,
+                               const double* va, int64_t m, int64_t n,
+                               const int64_t* rpt, unsigned long long* cursor,
+                               int* cit, double* vat, int* err, hipStream_t s);
+void launch_csr_coarsen(const int64_t* rp, const int* ci, const double* va,
+                        int64_t m, int nvf, int nhf, int periodic, int mode,
+                        int64_t* cnt, const int64_t* rpc, int* cic,
+                        double* vac, int* err, hipStream_t s);
+void launch_row_sumsq(const int64_t* rpt, const double* vat, int64_t n,
+                      double* out, hipStream_t s);
+template <class VT, class XT, class YT>
+void launch_spmv(const int64_t* rp, const int* ci, const VT* va, int64_t nrows,
+                 int64_t xstride, const XT* x, int x_shared, int64_t ystride,
+                 YT* y, int nslot, const int* slots, const int* active,
+                 hipStream_t s);
+void launch_dense_gram(const int64_t* rpt, const int* cit, const double* vat,
+                       int nc, double* G, hipStream_t s);
+void launch_f64_from_f32(const float* a, int64_t n, double* b, hipStream_t s);
+void launch_ct_apply(int pro, int epi, const ApplyArgsT<double>& a,
+                     hipStream_t s);
+void launch_ct_apply(int pro, int epi, const ApplyArgsT<float>& a,
+                     hipStream_t s);
+int ct_parts(int64_t n);   // partial sums per slot of a sparse-level kernel
+void launch_gershgorin_ct(const LevelGeom& g, const double* lam2, int nslot,
+                          double* rho, hipStream_t s);
+void launch_coarse_assemble_ct(const LevelGeom& g, const double* G,
+                               const double* lam2, int nslot, double* Kc,
+                               hipStream_t s);
 
 // FP32 V-cycle boundary (k_pcg.hip)
 void launch_to_f32(const double* src, int64_t n, int nslot, const int* slots,

@@ -1,0 +1,103 @@
+"""Tomography (sparse A) path against the oracle.
+
+The projector is generated once on the CPU and handed to both sides.  On
+the GPU the one-sided hierarchy A_{k+1} = A_k P and every A_k^T are built
+by the library; the level operators K_k(lambda) must match the oracle's
+SciPy products to relative 1e-12, the FP32 V-cycle the oracle's FP64
+V-cycle to single-precision accuracy (3e-5 of the largest entry, as for the
+deblurring path), and the sweep solutions the oracle's dense solves to
+relative 1e-6 (FP64 PCG with the FP32 V-cycle, relative residual 1e-13).
+"""
+import numpy as np
+import pytest
+
+from oracle.pcg import CtOracle
+from tests.gpu_util import dev, host
+from workloads.ct import small_ct
+
+pytestmark = pytest.mark.gpu
+
+
+def _prob(P, ell, levels, nu=2, ratio=4.0):
+    from paper_2306_11067_amd import TomographyProblem
+    return TomographyProblem(P.rowptr, P.col, P.val, P.N, levels, nu=nu,
+                             cheb_ratio=ratio, weights=dev(P.weights[ell]))
+
+
+@pytest.fixture(scope="module")
+def case():
+    P = small_ct(32, 24, 3, 4)
+    return P, _prob(P, 1, 3), CtOracle(P.matrix(), P.N, P.lbc, P.weights[1], 3)
+
+
+def test_ct_forward_adjoint_match_scipy(case):
+    P, prob, O = case
+    rng = np.random.default_rng(1)
+    A = P.matrix()
+    x = rng.standard_normal(2 * P.n)
+    y = rng.standard_normal(2 * P.m)
+    ax = host(prob.forward(dev(x), nvec=2))
+    aty = host(prob.adjoint(dev(y), nvec=2))
+    for s in range(2):
+        want = A @ x[s * P.n:(s + 1) * P.n]
+        np.testing.assert_allclose(ax[s * P.m:(s + 1) * P.m], want, rtol=0,
+                                   atol=1e-12 * np.abs(want).max())
+        want = A.T @ y[s * P.m:(s + 1) * P.m]
+        np.testing.assert_allclose(aty[s * P.n:(s + 1) * P.n], want, rtol=0,
+                                   atol=1e-12 * np.abs(want).max())
+
+
+def test_ct_level_operators_match_oracle(case):
+    P, prob, O = case
+    H = O.H
+    rng = np.random.default_rng(2)
+    lams = np.array([1e-3, 0.3, 40.0])
+    for k in range(H.levels):
+        nk = H.nv[k] * H.nh[k]
+        v = rng.standard_normal(len(lams) * nk)
+        got = host(prob.apply_normal(k, lams, dev(v))).reshape(len(lams), nk)
+        for s, lam in enumerate(lams):
+            want = H.K(k, lam, v[s * nk:(s + 1) * nk])
+            err = np.abs(got[s] - want).max() / np.abs(want).max()
+            assert err < 1e-12, (k, lam, err)
+
+
+def test_ct_gershgorin_matches_oracle(case):
+    P, prob, O = case
+    H = O.H
+    lams = np.array([1e-3, 0.1, 10.0])
+    for k in range(H.levels):
+        got = prob.gershgorin(k, lams)
+        want = np.array([H.gershgorin(k, lam) for lam in lams])
+        np.testing.assert_allclose(got, want, rtol=1e-12)
+
+
+def test_ct_fp32_vcycle_close_to_oracle(case):
+    P, prob, O = case
+    rng = np.random.default_rng(3)
+    lams = np.array([1e-3, 0.3, 40.0])
+    r = rng.standard_normal(len(lams) * P.n)
+    got = host(prob.vcycle(lams, dev(r))).reshape(len(lams), P.n)
+    for s, lam in enumerate(lams):
+        want = O.vcycle(lam, nu=2, ratio=4.0)(r[s * P.n:(s + 1) * P.n])
+        err = np.abs(got[s] - want).max() / np.abs(want).max()
+        assert 0.0 < err < 3e-5, (lam, err)
+
+
+@pytest.mark.parametrize("ell", [0, 1])
+def test_ct_sweep_matches_oracle(ell):
+    P = small_ct(64, 48, 4, 5)
+    prob = _prob(P, ell, 4, nu=4, ratio=16.0)
+    # the edge-weighted system reaches an error/residual ratio ~1e6 at
+    # lambda = 1e-3, so the residual target is 1e-13
+    x, res, sem, info = prob.solve_sweep(dev(P.b), P.lams, 1e-13, poll_every=8)
+    x = host(x)
+    O = CtOracle(P.matrix(), P.N, P.lbc, P.weights[ell], 4)
+    for s, lam in enumerate(P.lams):
+        xr, rel = O.reference(P.b, lam)
+        assert rel < 1e-11
+        e = np.linalg.norm(x[s] - xr) / np.linalg.norm(xr)
+        assert e <= 1e-6, (ell, lam, e, info[s])
+        rho, eta = O.pair(xr, P.b)
+        assert abs(res[s] - rho) <= 1e-6 * rho and abs(sem[s] - eta) <= 1e-6 * eta
+        assert info[s]["flags"] & 1, info[s]
