@@ -421,6 +421,158 @@ k_cholesky_inverse(double* __restrict__ Kc, int n, double* __restrict__ work,
     if (t == 0) info[slot] = bad;
 }
 
+// Blocked variant for n a multiple of 16 on the FP64 matrix cores: the
+// trailing updates of the right-looking factorization and the block
+// products of W = L^{-1} run as 16 x 16 x 4 MFMA tiles (one wave per tile;
+// operand A element (i, k) on lane 16 k + i, operand B element (k, j) on
+// lane 16 k + j, result element (i, j) on lane 16 (i mod 4) + j, register
+// i / 4).  Diagonal blocks are factored / inverted in LDS.  Same outputs
+// as k_cholesky_inverse.
+typedef double v4d __attribute__((ext_vector_type(4)));
+
+__global__ void __launch_bounds__(256)
+k_cholesky_mfma(double* __restrict__ Kc, int n, double* __restrict__ work,
+                int* __restrict__ info) {
+    const int slot = blockIdx.x;
+    double* A = Kc + (size_t)slot * n * n;          // A(i, j) = A[j*n + i]
+    double* W = work + (size_t)slot * 2 * n * n;    // W(i, c) = W[i*n + c]
+    double* Wt = W + (size_t)n * n;
+    __shared__ double blk[16 * 17];
+    __shared__ double winv[16 * 17];
+    __shared__ int bad;
+    __shared__ double piv;
+    const int t = threadIdx.x, wave = t >> 6, lane = t & 63;
+    const int li = lane & 15, lk = lane >> 4;       // operand row/col, k group
+    const int nb = n / 16;
+    if (t == 0) bad = 0;
+    __syncthreads();
+    // ---- factorization ----------------------------------------------------
+    for (int kb = 0; kb < nb; ++kb) {
+        const int k0 = 16 * kb;
+        {
+            const int r = t & 15, c = t >> 4;
+            blk[c * 17 + r] = A[(size_t)(k0 + c) * n + k0 + r];
+        }
+        __syncthreads();
+        for (int c = 0; c < 16; ++c) {
+            if (t == 0) {
+                const double a = blk[c * 17 + c];
+                if (!(a > 0.0) || !isfinite(a)) {
+                    if (!bad) bad = k0 + c + 1;
+                    piv = 1.0;
+                } else {
+                    piv = sqrt(a);
+                }
+                blk[c * 17 + c] = piv;
+            }
+            __syncthreads();
+            if (t > c && t < 16) blk[c * 17 + t] /= piv;
+            __syncthreads();
+            {
+                const int r = t & 15, cc = t >> 4;
+                if (cc > c && r >= cc) blk[cc * 17 + r] -= blk[c * 17 + r] * blk[c * 17 + cc];
+            }
+            __syncthreads();
+        }
+        {
+            const int r = t & 15, c = t >> 4;
+            if (r >= c) A[(size_t)(k0 + c) * n + k0 + r] = blk[c * 17 + r];
+        }
+        // panel: L(i, k0:k0+16) = A(i, k0:k0+16) L_kk^{-T}
+        for (int i = k0 + 16 + t; i < n; i += 256) {
+            double x[16];
+#pragma unroll
+            for (int c = 0; c < 16; ++c) {
+                double a = A[(size_t)(k0 + c) * n + i];
+                for (int m = 0; m < c; ++m) a -= x[m] * blk[m * 17 + c];
+                x[c] = a / blk[c * 17 + c];
+            }
+#pragma unroll
+            for (int c = 0; c < 16; ++c) A[(size_t)(k0 + c) * n + i] = x[c];
+        }
+        __syncthreads();
+        // trailing update of the lower tiles (I, J), kb < J <= I < nb
+        const int m = nb - kb - 1;
+        const int ntile = m * (m + 1) / 2;
+        for (int e = wave; e < ntile; e += 4) {
+            int Ir = (int)((sqrt(8.0 * e + 1.0) - 1.0) * 0.5);
+            while (Ir * (Ir + 1) / 2 > e) --Ir;
+            while ((Ir + 1) * (Ir + 2) / 2 <= e) ++Ir;
+            const int Jr = e - Ir * (Ir + 1) / 2;
+            const int I = kb + 1 + Ir, J = kb + 1 + Jr;
+            v4d acc;
+#pragma unroll
+            for (int r = 0; r < 4; ++r)
+                acc[r] = A[(size_t)(16 * J + li) * n + 16 * I + lk + 4 * r];
+#pragma unroll
+            for (int kk = 0; kk < 4; ++kk) {
+                const size_t col = (size_t)(k0 + 4 * kk + lk) * n;
+                const double a = -A[col + 16 * I + li];
+                const double b = A[col + 16 * J + li];
+                acc = __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, acc, 0, 0, 0);
+            }
+#pragma unroll
+            for (int r = 0; r < 4; ++r)
+                A[(size_t)(16 * J + li) * n + 16 * I + lk + 4 * r] = acc[r];
+        }
+        __syncthreads();
+    }
+    // ---- W = L^{-1}, block row by block row --------------------------------
+    for (int I = 0; I < nb; ++I) {
+        const int i0 = 16 * I;
+        {
+            const int r = t & 15, c = t >> 4;
+            blk[c * 17 + r] = r >= c ? A[(size_t)(i0 + c) * n + i0 + r] : 0.0;
+        }
+        __syncthreads();
+        if (t < 16) {   // column t of L_II^{-1} by forward substitution
+            const int c = t;
+            for (int i = 0; i < 16; ++i) {
+                double s = (i == c) ? 1.0 : 0.0;
+                if (i > c)
+                    for (int mm = c; mm < i; ++mm) s -= blk[mm * 17 + i] * winv[c * 17 + mm];
+                winv[c * 17 + i] = i < c ? 0.0 : s / blk[i * 17 + i];
+            }
+        }
+        __syncthreads();
+        {   // W_II and the zero blocks right of it
+            const int r = t & 15, c = t >> 4;
+            W[(size_t)(i0 + r) * n + i0 + c] = winv[c * 17 + r];
+            for (int cb = i0 + 16 + c; cb < n; cb += 16)
+                W[(size_t)(i0 + r) * n + cb] = 0.0;
+        }
+        // W_IJ = -W_II sum_{K=J}^{I-1} L_IK W_KJ
+        for (int J = wave; J < I; J += 4) {
+            v4d S = {0.0, 0.0, 0.0, 0.0};
+            for (int K = J; K < I; ++K) {
+#pragma unroll
+                for (int kk = 0; kk < 4; ++kk) {
+                    const int kr = 16 * K + 4 * kk + lk;
+                    const double a = A[(size_t)kr * n + i0 + li];
+                    const double b = W[(size_t)kr * n + 16 * J + li];
+                    S = __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, S, 0, 0, 0);
+                }
+            }
+            // S(k, j) for k = 4 kk + lk sits in register kk of this lane
+            v4d out = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+            for (int kk = 0; kk < 4; ++kk) {
+                const double a = -winv[(4 * kk + lk) * 17 + li];
+                out = __builtin_amdgcn_mfma_f64_16x16x4f64(a, S[kk], out, 0, 0, 0);
+            }
+#pragma unroll
+            for (int r = 0; r < 4; ++r)
+                W[(size_t)(i0 + lk + 4 * r) * n + 16 * J + li] = out[r];
+        }
+        __syncthreads();
+    }
+    for (int e = t; e < n * n; e += 256) {
+        const int i = e / n, c = e % n;
+        Wt[(size_t)c * n + i] = W[e];
+    }
+    if (t == 0) info[slot] = bad;
+}
+
 __global__ void k_check_weights(const double* __restrict__ d, int64_t n,
                                 int* __restrict__ bad) {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -505,6 +657,15 @@ void launch_coarse_assemble_ct(const LevelGeom& g, const double* G,
 }
 void launch_cholesky_inverse(double* Kc, int n, int nslot, double* work,
                              int* info, hipStream_t s) {
+    if (n % 16 == 0)
+        hipLaunchKernelGGL(k_cholesky_mfma, dim3(nslot), dim3(256), 0, s, Kc, n,
+                           work, info);
+    else
+        hipLaunchKernelGGL(k_cholesky_inverse, dim3(nslot), dim3(1024), 0, s,
+                           Kc, n, work, info);
+}
+void launch_cholesky_inverse_scalar(double* Kc, int n, int nslot, double* work,
+                                    int* info, hipStream_t s) {
     hipLaunchKernelGGL(k_cholesky_inverse, dim3(nslot), dim3(1024), 0, s, Kc,
                        n, work, info);
 }
