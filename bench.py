@@ -6,9 +6,9 @@ piecewise-constant phantom with 1% noise, three outer weightings
 (D = I, then seeded edge weights in [0.01, 1]) and 20 lambdas log-spaced in
 [1e-5, 1]; a six-level V-cycle preconditioner.  One step = for every outer
 weighting: install the weights (Galerkin hierarchy) and solve the whole
-lambda sweep to relative residual 1e-12, the tolerance at which every
+lambda sweep to relative residual 4e-13, a tolerance at which every
 solution is within relative error 1e-6 of the FP64 oracle (checked by the
-GPU test suite at this size).  Each weighting's sweep starts from the
+GPU test suite at this size and setting).  Each weighting's sweep starts from the
 previous weighting's solutions (warm start across outer iterations).
 60 solves per step, FP64 throughout.
 
@@ -33,8 +33,8 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
 
-TOL = 1e-12
-NU_FINE, RATIO_FINE = 32, 400.0
+TOL = 4e-13
+NU_FINE, RATIO_FINE = 128, 3.0e5
 NU_COARSE, RATIO_COARSE = 2, 4.0
 HBM_PEAK_GBS = 8000.0
 COPY_PROBE_BYTES = 256 << 20    # calibration copy for the traffic counters

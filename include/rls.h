@@ -117,12 +117,12 @@ typedef struct {
                                unknowns, every level at least 4 x 4          */
     int nu;                 /* Chebyshev smoothing steps before and after the
                                coarse correction on the finest level
-                               (V(nu,nu)), 1..64                            */
+                               (V(nu,nu)), 1..256                            */
     double cheb_ratio;      /* finest-level smoothing interval
                                [rho/ratio, rho], rho the Gershgorin bound of
                                diag(K_k)^-1 K_k; > 1                         */
     int precision;          /* RLS_PREC_FP64 or RLS_PREC_MIXED_FP32          */
-    int nu_coarse;          /* same on the coarser levels (0: = nu), 1..64  */
+    int nu_coarse;          /* same on the coarser levels (0: = nu), 1..256 */
     double cheb_ratio_coarse; /* same on the coarser levels (0: = cheb_ratio) */
 } rls_grid_desc;
 

@@ -931,9 +931,9 @@ void vcycle(rls_problem* P, int k, int nslot, const int* slots,
 rls_status validate_grid(const rls_grid_desc* g) {
     if (g->nv < 4 || g->nh < 4) return fail(RLS_E_ARG, "grid must be >= 4 x 4");
     if (g->levels < 1 || g->levels > 16) return fail(RLS_E_ARG, "levels in 1..16");
-    if (g->nu < 1 || g->nu > 64) return fail(RLS_E_ARG, "nu in 1..64");
-    if (g->nu_coarse < 0 || g->nu_coarse > 64)
-        return fail(RLS_E_ARG, "nu_coarse in 0..64");
+    if (g->nu < 1 || g->nu > 256) return fail(RLS_E_ARG, "nu in 1..256");
+    if (g->nu_coarse < 0 || g->nu_coarse > 256)
+        return fail(RLS_E_ARG, "nu_coarse in 0..256");
     if (!(g->cheb_ratio > 1.0) || !std::isfinite(g->cheb_ratio))
         return fail(RLS_E_ARG, "cheb_ratio must be > 1");
     if (g->cheb_ratio_coarse != 0.0 &&

@@ -2,7 +2,7 @@
 
 The 512 x 512 deblurring workload (3 outer weightings x 20 lambdas in
 [1e-5, 1]) is solved on the GPU exactly as bench.py does (same smoothing
-settings, relative residual 1e-12, graph-replayed iteration chunks, each
+settings and relative residual, graph-replayed iteration chunks, each
 weighting's sweep warm-started from the previous one's solutions), in FP64
 and with the FP32 V-cycle under flexible PCG, and
 every one of the 60 solutions is compared with the oracle's x*(lambda)
