@@ -36,6 +36,7 @@ if ROOT not in sys.path:
 TOL = 4e-13
 NU_FINE, RATIO_FINE = 128, 3.0e5
 NU_COARSE, RATIO_COARSE = 2, 4.0
+CT_TOL = 1e-12
 HBM_PEAK_GBS = 8000.0
 COPY_PROBE_BYTES = 256 << 20    # calibration copy for the traffic counters
 
@@ -141,6 +142,64 @@ def cpu_baseline(P_, iters_per_slot, budget_s=20.0):
     }
 
 
+def run_ct(args):
+    """The tomography sweep: every weighting warm-started from the previous
+    one, relative residual CT_TOL, the benchmark's smoothing."""
+    import numpy as np
+    import torch
+
+    from paper_2306_11067_amd import TomographyProblem
+    from workloads.ct import config3
+
+    P = config3()
+    dev = torch.device("cuda:0")
+    b = torch.as_tensor(P.b).to(dev)
+    D = [torch.as_tensor(w).to(dev) for w in P.weights]
+    lams = np.asarray(P.lams)
+    prob = TomographyProblem(P.rowptr, P.col, P.val, P.N, P.levels,
+                             nu=NU_FINE, cheb_ratio=RATIO_FINE, weights=D[0],
+                             nu_coarse=NU_COARSE,
+                             cheb_ratio_coarse=RATIO_COARSE)
+    bufs = [torch.empty(len(lams) * P.n, dtype=torch.float64, device=dev)
+            for _ in range(2)]
+    prob.solve_sweep(b, lams, CT_TOL, maxit=2, poll_every=2)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    infos = []
+    for _ in range(args.steps):
+        infos, x0 = [], None
+        for k, d in enumerate(D):
+            prob.set_weights(d)
+            x, _, _, info = prob.solve_sweep(b, lams, CT_TOL, x0=x0,
+                                             x=bufs[k & 1], maxit=400000,
+                                             poll_every=16)
+            x0 = x
+            infos.append(info)
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+    solves = args.steps * len(lams) * len(D)
+    iters = [i["iters"] for info in infos for i in info]
+    out = {
+        "metric": "lambda-sweep PCG solves/sec (tomography workload)",
+        "value": solves / elapsed, "unit": "solves/s", "n_gpus": 1,
+        "steps": args.steps, "warmup": 0,
+        "ms_per_step": 1e3 * elapsed / args.steps, "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": "f64+f32",
+        "data": "synthetic (seeded ellipse phantom, exact-length projector)",
+        "config": {"workload": (f"CT {P.N}x{P.N} parallel beam, "
+                                f"{P.n_angles} angles x {P.n_bins} bins, "
+                                f"nnz {int(P.rowptr[-1])}, {len(P.weights)} "
+                                f"weightings x {len(lams)} lambdas in "
+                                f"[1e-3, 1e2], {P.levels} levels, Chebyshev "
+                                f"nu={NU_FINE}, rel. residual {CT_TOL:g}"),
+                   "max_iterations": max(iters),
+                   "all_converged": all(i["flags"] & 1 for info in infos
+                                        for i in info)},
+        "roofline": None, "cpu_baseline": None,
+    }
+    print(json.dumps(out), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -149,6 +208,11 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-roofline", action="store_true")
     ap.add_argument("--no-mixed", action="store_true")
+    ap.add_argument("--workload", default="deblur512",
+                    choices=["deblur512", "ct256"],
+                    help="ct256: the 256x256 parallel-beam tomography sweep "
+                         "(32 lambdas, 2 weightings, FP32 V-cycle under FP64 "
+                         "PCG); prints its own JSON line without roofline")
     ap.add_argument("--traffic-probe", action="store_true",
                     help="only run the launches the HBM traffic counters are "
                          "taken on (a copy of known size, then 4 iterations "
@@ -164,6 +228,9 @@ def main():
 
     import workloads as W
     from paper_2306_11067_amd import Problem
+
+    if args.workload == "ct256":
+        return run_ct(args)
 
     P_ = W.config2()
     dev = torch.device("cuda:0")

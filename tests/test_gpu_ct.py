@@ -101,3 +101,28 @@ def test_ct_sweep_matches_oracle(ell):
         rho, eta = O.pair(xr, P.b)
         assert abs(res[s] - rho) <= 1e-6 * rho and abs(sem[s] - eta) <= 1e-6 * eta
         assert info[s]["flags"] & 1, info[s]
+
+
+def test_ct_full_size_properties():
+    # The 256 x 256 parallel-beam workload (180 angles, 363 bins, 1.5e7
+    # nonzeros) with the benchmark's smoothing on three lambdas of its
+    # sweep.  No closed form exists at this size, so the oracle checks what
+    # holds at any size: its own FP64 residual of the normal equations at the
+    # GPU's x (<= the tolerance, up to rounding) and the L-curve pair.
+    import bench
+    from workloads.ct import config3
+    P = config3()
+    lams = np.array([1e-1, 3.0, 100.0])
+    prob = _prob(P, 1, P.levels, nu=bench.NU_FINE, ratio=bench.RATIO_FINE)
+    tol = 1e-12
+    x, res, sem, info = prob.solve_sweep(dev(P.b), lams, tol, poll_every=16)
+    x = host(x)
+    O = CtOracle(P.matrix(), P.N, P.lbc, P.weights[1], 1)
+    f = O.rhs(P.b)
+    for s, lam in enumerate(lams):
+        assert info[s]["flags"] & 1, info[s]
+        r = f - O.K(lam)(x[s])
+        rel = np.linalg.norm(r) / np.linalg.norm(f)
+        assert rel <= 1.05 * tol, (lam, rel)
+        rho, eta = O.pair(x[s], P.b)
+        assert abs(res[s] - rho) <= 1e-10 * rho and abs(sem[s] - eta) <= 1e-10 * eta
