@@ -148,6 +148,12 @@ typedef struct rls_problem rls_problem;
  * the blur, paper Section 3.2 one-sided hierarchy) and install the weights.
  * d: device, 2n values >= 0 and finite, or NULL for D = I (paper D^(0) = I).
  * On success *out receives a handle to free with rls_destroy.
+ * Kernel choice: the finest-level Chebyshev step of a blur problem takes a
+ * tiled kernel specialised for the band radius when the grid is a whole
+ * number of 64 x 16 tiles and the Gram bands are uniform (periodic, or
+ * reflective with a symmetric PSF); the environment variable
+ * RLS_FINE_KERNEL=generic, read here, makes this problem use the general
+ * level-operator kernel instead (same arithmetic up to rounding).
  * Errors: RLS_E_ARG (bad sizes, radii >= n/2, non-finite taps, nu/levels out
  * of range), RLS_E_UNSUPPORTED (sparse operator, precision), RLS_E_OOM,
  * RLS_E_HIP. */

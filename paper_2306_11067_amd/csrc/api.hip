@@ -4,6 +4,7 @@
 #include <algorithm>
 #include <cmath>
 #include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <memory>
 #include <string>
@@ -236,6 +237,9 @@ struct rls_problem {
     std::vector<double> ratio;   // Chebyshev interval ratio per level
     int nu_max = 2;
     int periodic = 0;            // multigrid / gradient periodicity
+    // RLS_FINE_KERNEL=generic at set-up: the finest-level Chebyshev step
+    // always takes the general level-operator kernel
+    int fine_generic = 0;
     int r_v = 0, r_h = 0;
     std::vector<double> taps_v, taps_h;
     std::vector<Level> lev;
@@ -317,12 +321,14 @@ void smooth_fine(rls_problem* P, const ApplyArgs& a, hipStream_t s) {
         launch_ct_apply(PRO_PLAIN, EPI_CHEB, a, s);
         return;
     }
-    launch_smooth_fine(a, s);
+    if (P->fine_generic) launch_apply(PRO_PLAIN, EPI_CHEB, a, s);
+    else launch_smooth_fine(a, s);
     if (P->timer_on) P->run_cur.launches += 1;
 }
 // FP32 V-cycle: not timed (the kernel timer covers the FP64 step).
-void smooth_fine(rls_problem*, const ApplyArgsT<float>& a, hipStream_t s) {
+void smooth_fine(rls_problem* P, const ApplyArgsT<float>& a, hipStream_t s) {
     if (a.g.ct.on) launch_ct_apply(PRO_PLAIN, EPI_CHEB, a, s);
+    else if (P->fine_generic) launch_apply(PRO_PLAIN, EPI_CHEB, a, s);
     else launch_smooth_fine(a, s);
 }
 
@@ -1131,6 +1137,10 @@ rls_status rls_setup(rls_problem** out, const rls_op_desc* A,
     P->bc = A->bc;
     P->lbc = g->lbc;
     P->periodic = g->lbc == RLS_L_PERIODIC;
+    {
+        const char* e = std::getenv("RLS_FINE_KERNEL");
+        P->fine_generic = e && std::strcmp(e, "generic") == 0;
+    }
     P->r_v = A->r_v;
     P->r_h = A->r_h;
     P->taps_v.assign(A->taps_v, A->taps_v + 2 * A->r_v + 1);

@@ -618,16 +618,6 @@ __global__ void RLS_APPLY_BOUNDS_T(R) k_apply(ApplyArgsT<R> a) {
     apply_body<PRO, EPI, R>(a, reinterpret_cast<R*>(lds_raw), red);
 }
 
-// The finest-level Chebyshev step (plain prologue) under a name of its own,
-// so that profiles separate the sweep's most frequent kernel from the same
-// step on coarser levels.
-template <class R>
-__global__ void RLS_APPLY_BOUNDS_T(R) k_smooth_fine(ApplyArgsT<R> a) {
-    extern __shared__ double lds_raw[];
-    __shared__ double red[APPLY_THREADS];
-    apply_body<PRO_PLAIN, EPI_CHEB, R>(a, reinterpret_cast<R*>(lds_raw), red);
-}
-
 // dynamic LDS may use what the kernel's static LDS leaves of 160 KiB
 static void allow_lds(const void* fn) {
     hipFuncAttributes attr;
@@ -677,8 +667,6 @@ void configure_apply_kernels() {
     RLS_APPLY_VARIANTS_F32(RLS_CFG32)
 #undef RLS_CFG64
 #undef RLS_CFG32
-    allow_lds((const void*)k_smooth_fine<double>);
-    allow_lds((const void*)k_smooth_fine<float>);
     (void)hipGetLastError();
     done = true;
 }
@@ -700,19 +688,15 @@ size_t apply_lds_bytes(const LevelGeomT<float>& g, int epi) {
     return sizeof(float) * T.lds_elems();
 }
 
-template <class R>
-static void smooth_fine_impl(const ApplyArgsT<R>& a, hipStream_t s) {
-    const TileShape T(a.g, 0);
-    dim3 grid((a.g.nv + TILE_Y - 1) / TILE_Y, (a.g.nh + TILE_X - 1) / TILE_X,
-              a.nslot);
-    hipLaunchKernelGGL(k_smooth_fine<R>, grid, dim3(APPLY_THREADS),
-                       sizeof(R) * T.lds_elems(), s, a);
-}
+// Finest-level Chebyshev step: the tiled kernel with a compile-time band
+// radius where it applies, the general kernel otherwise.
 void launch_smooth_fine(const ApplyArgsT<double>& a, hipStream_t s) {
-    smooth_fine_impl(a, s);
+    if (!launch_smooth_fine_tiled(a, s))
+        launch_one<PRO_PLAIN, EPI_CHEB, double>(a, s);
 }
 void launch_smooth_fine(const ApplyArgsT<float>& a, hipStream_t s) {
-    smooth_fine_impl(a, s);
+    if (!launch_smooth_fine_tiled(a, s))
+        launch_one<PRO_PLAIN, EPI_CHEB, float>(a, s);
 }
 
 void launch_apply(int pro, int epi, const ApplyArgsT<double>& a, hipStream_t s) {

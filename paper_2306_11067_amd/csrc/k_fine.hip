@@ -1,0 +1,353 @@
+// Finest-level Chebyshev smoothing step, specialised for a compile-time band
+// radius.  This is the step the V-cycle (paper Algorithm 1, smoothing on the
+// finest level) repeats most often: with the plain prologue and the
+// Chebyshev epilogue it computes, per lambda slot,
+//     d <- c1 d + c2 (f - K x) / diag(K),   x_out = x + d,
+// with K = G_h (x) G_v + lambda^2 S (paper Section 3.2: the separable Gram
+// of the blur plus the five-point stencil of L^T D^2 L on the fine grid).
+//
+// It applies when both Gram bands of the level are uniform (one row of taps
+// plus a wrap or reflection index map), the stencil has five points and the
+// grid is a whole number of 64 x 16 tiles; the level-operator kernel covers
+// every other case with the same arithmetic.
+//
+// Differences from the general kernel, all aimed at fewer instructions per
+// output point:
+//   * the band radius BW is a template parameter: the tap loops unroll, and
+//     the taps (symmetric, so BW + 1 per direction) sit in scalar registers;
+//   * the tile and its halo are loaded as units of 16 bytes of one row
+//     (VEC consecutive columns, one load per column, one 16-byte LDS write),
+//     spread evenly over the 256 threads, with branch-free wrap / reflect
+//     index maps;
+//   * the vertical pass gives every thread 4 consecutive rows of one column,
+//     so all four waves work, and its results stay in registers: the
+//     stencil term and the Chebyshev update follow directly, with 16-byte
+//     global loads and stores of the 4 rows.
+#include "common.h"
+
+namespace rls {
+namespace {
+
+constexpr int FY = 64;    // output rows per tile (contiguous axis)
+constexpr int FX = 16;    // output columns per tile
+constexpr int FT = 256;   // threads
+constexpr int HWO = 8;    // horizontal-pass outputs per thread
+constexpr int VWO = 4;    // vertical-pass outputs per thread
+
+template <class R>
+struct Vec16;
+template <>
+struct Vec16<double> {
+    using T = double2;
+};
+template <>
+struct Vec16<float> {
+    using T = float4;
+};
+
+template <class R, int BW>
+struct FineShape {
+    static constexpr int VEC = 16 / (int)sizeof(R);   // elements per 16 bytes
+    static constexpr int RY = FY + 2 * BW;            // input rows
+    static constexpr int CX = FX + 2 * BW;            // input columns
+    // Row stride of the input tile and column stride of the horizontal-pass
+    // result: whole 16-byte units, an odd number of them, so that eight
+    // lanes reading 16 bytes each at that stride hit eight distinct groups
+    // of four LDS banks.
+    static constexpr int SX = (((CX + VEC - 1) / VEC) | 1) * VEC;
+    static constexpr int SH = (((RY + VEC - 1) / VEC) | 1) * VEC;
+    static constexpr int NU = RY * (CX / VEC);        // load units
+    static constexpr int UPT = (NU + FT - 1) / FT;    // units per thread
+    static constexpr int HWL = HWO + 2 * BW;          // horizontal window
+    static constexpr int VWL = VWO + 2 * BW;          // vertical window
+    static constexpr size_t lds_bytes =
+        sizeof(R) * ((size_t)RY * SX + (size_t)FX * SH);
+    static_assert(BW % 2 == 0, "even band radius");
+    static_assert(CX % VEC == 0, "whole load units per row");
+    static_assert(HWL % VEC == 0 && VWL % VEC == 0, "whole vector windows");
+    static_assert(2 * RY <= FT, "one horizontal item per thread");
+    static_assert((FY / VWO) * FX == FT, "one vertical item per thread");
+};
+
+// Position x in [-n, 2n) of an axis of length n under the band's index map:
+// periodic wrap, or half-sample reflection.
+__device__ __forceinline__ int fine_map(int x, int n, bool wrap) {
+    const int lo = wrap ? x + n : -1 - x;
+    const int hi = wrap ? x - n : 2 * n - 1 - x;
+    return x < 0 ? lo : (x >= n ? hi : x);
+}
+
+// Four consecutive elements at a 16-byte aligned element index.
+template <class R>
+__device__ __forceinline__ void ld4(const R* base, uint32_t idx, R (&o)[4]) {
+    const char* p =
+        reinterpret_cast<const char*>(base) + idx * (uint32_t)sizeof(R);
+    if constexpr (sizeof(R) == 8) {
+        const double2 a = *reinterpret_cast<const double2*>(p);
+        const double2 b = *reinterpret_cast<const double2*>(p + 16);
+        o[0] = a.x; o[1] = a.y; o[2] = b.x; o[3] = b.y;
+    } else {
+        const float4 a = *reinterpret_cast<const float4*>(p);
+        o[0] = a.x; o[1] = a.y; o[2] = a.z; o[3] = a.w;
+    }
+}
+
+template <class R>
+__device__ __forceinline__ void st4(R* base, uint32_t idx, const R (&v)[4]) {
+    char* p = reinterpret_cast<char*>(base) + idx * (uint32_t)sizeof(R);
+    if constexpr (sizeof(R) == 8) {
+        *reinterpret_cast<double2*>(p) = make_double2(v[0], v[1]);
+        *reinterpret_cast<double2*>(p + 16) = make_double2(v[2], v[3]);
+    } else {
+        *reinterpret_cast<float4*>(p) = make_float4(v[0], v[1], v[2], v[3]);
+    }
+}
+
+template <class R>
+__device__ __forceinline__ R ldg(const R* base, uint32_t idx) {
+    return *reinterpret_cast<const R*>(reinterpret_cast<const char*>(base) +
+                                       idx * (uint32_t)sizeof(R));
+}
+
+// n consecutive LDS elements from a 16-byte aligned address.
+template <class R, int N>
+__device__ __forceinline__ void lds_window(const R* p, R (&w)[N]) {
+    using V = typename Vec16<R>::T;
+    constexpr int VEC = 16 / (int)sizeof(R);
+    static_assert(N % VEC == 0, "whole vectors");
+#pragma unroll
+    for (int m = 0; m < N / VEC; ++m) {
+        const V x = reinterpret_cast<const V*>(p)[m];
+        if constexpr (VEC == 2) {
+            w[2 * m] = x.x; w[2 * m + 1] = x.y;
+        } else {
+            w[4 * m] = x.x; w[4 * m + 1] = x.y;
+            w[4 * m + 2] = x.z; w[4 * m + 3] = x.w;
+        }
+    }
+}
+
+template <class R, int BW>
+__global__ void __launch_bounds__(FT)
+k_smooth_fine(ApplyArgsT<R> a) {
+    using S = FineShape<R, BW>;
+    using V = typename Vec16<R>::T;
+    extern __shared__ __align__(16) double lds_raw[];
+    __shared__ double red[FT];
+    R* vin = reinterpret_cast<R*>(lds_raw);      // RY x SX, row-major
+    R* ht = vin + S::RY * S::SX;                 // FX x SH, column-major
+    const int t = threadIdx.x;
+    const int z = blockIdx.z;
+    const int slot = z < a.zn ? a.zslot[z] : a.slots ? a.slots[z] : z;
+    const LevelGeomT<R>& g = a.g;
+    const int nv = g.nv, nh = g.nh;
+    // XCD-aware tile order, as in the general kernel
+    const int ntx = gridDim.x, nty = gridDim.y, ntile = ntx * nty;
+    int tile = blockIdx.x + ntx * blockIdx.y;
+    if ((ntile & 7) == 0) tile = (tile & 7) * (ntile >> 3) + (tile >> 3);
+    const int tx = tile % ntx, ty = tile / ntx;
+    const int i0 = tx * FY, j0 = ty * FX;
+    const size_t so = (size_t)slot * ((size_t)nv * nh);
+    const R* src = a.in + so;
+    const R* f = a.f_shared ? a.f : a.f + so;
+    R* dir = a.d + so;
+    R* out = a.out + so;
+    const bool wrapv = g.gv.map == MAP_WRAP, wraph = g.gh.map == MAP_WRAP;
+    const int per = g.S.periodic;
+
+    // 1. operands of this thread's four outputs (rows r0..r0+3 of column c),
+    //    requested first: right-hand side, direction, diagonals, couplings.
+    const int c = t & (FX - 1), r0 = VWO * (t >> 4);
+    const int gi0 = i0 + r0, gj = j0 + c;
+    const uint32_t p0 = (uint32_t)gi0 + (uint32_t)nv * (uint32_t)gj;
+    R pf[4], pd[4], psc[4], psn[4], pse[4], psw[4], dgv[4];
+    ld4(f, p0, pf);
+    ld4((const R*)dir, p0, pd);
+    ld4(g.S.c, p0, psc);
+    ld4(g.S.cn, p0, psn);
+    ld4(g.S.ce, p0, pse);
+    ld4(g.gv.diag, (uint32_t)gi0, dgv);
+    const R dgh = g.gh.diag[gj];
+    // south coupling of the first row (the north coupling one row down) and
+    // west couplings (the east couplings one column left): wrapped on a
+    // periodic grid, zero across a non-periodic edge
+    R pss0 = R(0);
+    if (gi0 > 0) pss0 = ldg(g.S.cn, p0 - 1);
+    else if (per) pss0 = ldg(g.S.cn, (uint32_t)(nv - 1) + (uint32_t)nv * gj);
+    if (gj > 0) {
+        ld4(g.S.ce, p0 - (uint32_t)nv, psw);
+    } else if (per) {
+        ld4(g.S.ce, (uint32_t)gi0 + (uint32_t)nv * (uint32_t)(nh - 1), psw);
+    } else {
+#pragma unroll
+        for (int o = 0; o < 4; ++o) psw[o] = R(0);
+    }
+
+    // 2. the tile plus its halo of BW rows and columns, as units of VEC
+    //    consecutive columns of one row, all loads in flight at once
+    R u[S::UPT][S::VEC];
+#pragma unroll
+    for (int k = 0; k < S::UPT; ++k) {
+        const int e = t + FT * k;
+#pragma unroll
+        for (int cc = 0; cc < S::VEC; ++cc) u[k][cc] = R(0);
+        if (e < S::NU) {
+            const int ii = e % S::RY, jq = e / S::RY;
+            const uint32_t gi = (uint32_t)fine_map(i0 - BW + ii, nv, wrapv);
+#pragma unroll
+            for (int cc = 0; cc < S::VEC; ++cc) {
+                const int gjj = fine_map(j0 - BW + jq * S::VEC + cc, nh, wraph);
+                u[k][cc] = ldg(src, gi + (uint32_t)nv * (uint32_t)gjj);
+            }
+        }
+    }
+    // uniform taps, half row plus centre (the Gram rows are symmetric);
+    // positions beyond a direction's own radius are zero
+    R tv[BW + 1], th[BW + 1];
+#pragma unroll
+    for (int k = 0; k <= BW; ++k) {
+        const int kv = k - (BW - g.gv.bw), kh = k - (BW - g.gh.bw);
+        tv[k] = kv >= 0 ? g.gv.taps[kv] : R(0);
+        th[k] = kh >= 0 ? g.gh.taps[kh] : R(0);
+    }
+    const R l2 = (R)a.lam2[slot];
+    const R cd = (R)a.cheb[(size_t)slot * a.cheb_stride];
+    const R cr = (R)a.cheb[(size_t)slot * a.cheb_stride + 1];
+    // a slot that stopped inside a replayed chunk is skipped (its loads
+    // above are harmless, its stores are not)
+    if (a.active && !a.active[slot]) return;
+#pragma unroll
+    for (int k = 0; k < S::UPT; ++k) {
+        const int e = t + FT * k;
+        if (e < S::NU) {
+            const int ii = e % S::RY, jq = e / S::RY;
+            V x;
+            if constexpr (S::VEC == 2) {
+                x.x = u[k][0]; x.y = u[k][1];
+            } else {
+                x.x = u[k][0]; x.y = u[k][1]; x.z = u[k][2]; x.w = u[k][3];
+            }
+            *reinterpret_cast<V*>(vin + ii * S::SX + jq * S::VEC) = x;
+        }
+    }
+    __syncthreads();
+
+    // 3. horizontal pass over the tile's columns and every input row:
+    //    ht(q, cc) = sum_k G_h(k) v(q, cc + k), k = 0..2BW
+    if (t < 2 * S::RY) {
+        const int hsel = t >= S::RY;
+        const int q = t - hsel * S::RY;
+        const int c0 = hsel * HWO;
+        R w[S::HWL];
+        lds_window<R, S::HWL>(vin + q * S::SX + c0, w);
+        R acc[HWO];
+#pragma unroll
+        for (int o = 0; o < HWO; ++o) acc[o] = th[BW] * w[o + BW];
+#pragma unroll
+        for (int k = 0; k < BW; ++k)
+#pragma unroll
+            for (int o = 0; o < HWO; ++o)
+                acc[o] = fma(th[k], w[o + k] + w[o + 2 * BW - k], acc[o]);
+#pragma unroll
+        for (int o = 0; o < HWO; ++o) ht[(c0 + o) * S::SH + q] = acc[o];
+    }
+    __syncthreads();
+
+    // 4. vertical pass for rows r0..r0+3 of column c
+    R kv[VWO];
+    {
+        R w[S::VWL];
+        lds_window<R, S::VWL>(ht + c * S::SH + r0, w);
+#pragma unroll
+        for (int o = 0; o < VWO; ++o) kv[o] = tv[BW] * w[o + BW];
+#pragma unroll
+        for (int k = 0; k < BW; ++k)
+#pragma unroll
+            for (int o = 0; o < VWO; ++o)
+                kv[o] = fma(tv[k], w[o + k] + w[o + 2 * BW - k], kv[o]);
+    }
+
+    // 5. stencil term, Chebyshev update, stores
+    const R* vc = vin + (r0 + BW) * S::SX + c + BW;
+    R colv[VWO + 2];
+#pragma unroll
+    for (int o = 0; o < VWO + 2; ++o) colv[o] = vc[(o - 1) * S::SX];
+    R nd[4], nx[4];
+    double dot = 0.0;
+#pragma unroll
+    for (int o = 0; o < VWO; ++o) {
+        const R v = colv[o + 1];
+        const R ss = o == 0 ? pss0 : psn[o - 1];
+        R sv = psc[o] * v;
+        sv += psn[o] * colv[o + 2];
+        sv += ss * colv[o];
+        sv += pse[o] * vc[o * S::SX + 1];
+        sv += psw[o] * vc[o * S::SX - 1];
+        const R kvo = kv[o] + l2 * sv;
+        const R dg = dgv[o] * dgh + l2 * psc[o];
+        nd[o] = cd * pd[o] + cr * (pf[o] - kvo) / dg;
+        nx[o] = v + nd[o];
+        dot += (double)pf[o] * (double)nx[o];
+    }
+    st4(dir, p0, nd);
+    st4(out, p0, nx);
+    if (a.dot) {
+        const double s = block_sum<FT>(dot, red);
+        if (t == 0) a.part[(size_t)slot * a.part_stride + tile] = s;
+    }
+}
+
+bool aligned16(const void* p) {
+    return ((uintptr_t)p & 15) == 0;
+}
+
+template <class R>
+int fine_radius(const ApplyArgsT<R>& a) {
+    const LevelGeomT<R>& g = a.g;
+    if (g.ct.on || !g.gv.uniform || !g.gh.uniform || g.S.nine) return -1;
+    if (g.gv.map == MAP_ZERO || g.gh.map == MAP_ZERO) return -1;
+    if (g.nv % FY != 0 || g.nh % FX != 0) return -1;
+    if (!a.in || !a.out || !a.d || !a.f || !a.cheb || !a.lam2) return -1;
+    const void* ptrs[] = {a.in, a.out, a.d, a.f, g.S.c, g.S.cn, g.S.ce,
+                          g.gv.diag};
+    for (const void* p : ptrs)
+        if (!aligned16(p)) return -1;
+    int bw = g.gv.bw > g.gh.bw ? g.gv.bw : g.gh.bw;
+    bw += bw & 1;
+    if (bw < 2) bw = 2;
+    return bw <= 16 ? bw : -1;
+}
+
+template <class R, int BW>
+void launch_fine(const ApplyArgsT<R>& a, hipStream_t s) {
+    using Sh = FineShape<R, BW>;
+    dim3 grid(a.g.nv / FY, a.g.nh / FX, a.nslot);
+    hipLaunchKernelGGL((k_smooth_fine<R, BW>), grid, dim3(FT), Sh::lds_bytes, s,
+                       a);
+}
+
+template <class R>
+bool fine_impl(const ApplyArgsT<R>& a, hipStream_t s) {
+    switch (fine_radius(a)) {
+        case 2: launch_fine<R, 2>(a, s); return true;
+        case 4: launch_fine<R, 4>(a, s); return true;
+        case 6: launch_fine<R, 6>(a, s); return true;
+        case 8: launch_fine<R, 8>(a, s); return true;
+        case 10: launch_fine<R, 10>(a, s); return true;
+        case 12: launch_fine<R, 12>(a, s); return true;
+        case 14: launch_fine<R, 14>(a, s); return true;
+        case 16: launch_fine<R, 16>(a, s); return true;
+        default: return false;
+    }
+}
+
+}  // namespace
+
+bool launch_smooth_fine_tiled(const ApplyArgsT<double>& a, hipStream_t s) {
+    return fine_impl(a, s);
+}
+bool launch_smooth_fine_tiled(const ApplyArgsT<float>& a, hipStream_t s) {
+    return fine_impl(a, s);
+}
+
+}  // namespace rls

@@ -166,10 +166,16 @@ using ApplyArgs = ApplyArgsT<double>;
 void launch_apply(int pro, int epi, const ApplyArgsT<double>& a, hipStream_t s);
 void launch_apply(int pro, int epi, const ApplyArgsT<float>& a, hipStream_t s);
 void configure_apply_kernels();  // LDS limits of every variant, once
-// Finest-level Chebyshev step (plain prologue): same arithmetic as
-// launch_apply(PRO_PLAIN, EPI_CHEB), distinct kernel name.
+// Finest-level Chebyshev step (plain prologue, launch_apply(PRO_PLAIN,
+// EPI_CHEB) arithmetic): the tiled kernel of k_fine.hip when the level
+// qualifies (uniform bands of even radius <= 16 after padding, five-point
+// stencil, whole 64 x 16 tiles, 16-byte aligned vectors), else the general
+// kernel.
 void launch_smooth_fine(const ApplyArgsT<double>& a, hipStream_t s);
 void launch_smooth_fine(const ApplyArgsT<float>& a, hipStream_t s);
+// false when the level does not qualify (nothing launched)
+bool launch_smooth_fine_tiled(const ApplyArgsT<double>& a, hipStream_t s);
+bool launch_smooth_fine_tiled(const ApplyArgsT<float>& a, hipStream_t s);
 
 // ---- setup kernels (k_setup.hip) ------------------------------------
 void launch_blur_band(const double* taps, int r, int n, int bc, double* band,
