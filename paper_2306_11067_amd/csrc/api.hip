@@ -79,6 +79,8 @@ struct Band {
     size_t taps_off = 0;     // offset (in values) of the uniform row in table
     DBuf table, diag, rowabs;
     DBuf table32, diag32;    // FP32 copies (FP32 V-cycle)
+    std::vector<double> htaps;   // host copy of the uniform row
+    std::vector<float> htaps32;
     BandDev dev() const {
         BandDev b;
         b.n = n;
@@ -89,6 +91,7 @@ struct Band {
         b.taps = table.as<double>() + taps_off;
         b.diag = diag.as<double>();
         b.rowabs = rowabs.as<double>();
+        b.htaps = htaps.empty() ? nullptr : htaps.data();
         return b;
     }
     BandDevT<float> dev32() const {
@@ -100,6 +103,7 @@ struct Band {
         b.table = table32.as<float>();
         b.taps = table32.as<float>() + taps_off;
         b.diag = diag32.as<float>();
+        b.htaps = htaps32.empty() ? nullptr : htaps32.data();
         return b;
     }
 };
@@ -518,6 +522,14 @@ rls_status build_direction(rls_problem* P, const std::vector<double>& taps,
         } else {
             G.uniform = 0;
             G.map = MAP_ZERO;
+        }
+        if (G.uniform) {
+            G.htaps.resize(2 * bw + 1);
+            RLS_HIP(hipMemcpyAsync(G.htaps.data(), G.table.as<double>() + G.taps_off,
+                                   sizeof(double) * (2 * bw + 1),
+                                   hipMemcpyDeviceToHost, s));
+            RLS_HIP(hipStreamSynchronize(s));
+            G.htaps32.assign(G.htaps.begin(), G.htaps.end());
         }
         if (P->prec == RLS_PREC_MIXED_FP32) {
             const size_t tn = (size_t)nk * (2 * bw + 1);

@@ -33,6 +33,8 @@ constexpr int FX = 16;    // output columns per tile
 constexpr int FT = 256;   // threads
 constexpr int HWO = 8;    // horizontal-pass outputs per thread
 constexpr int VWO = 4;    // vertical-pass outputs per thread
+constexpr int FZ = 64;    // most slots per launch (the slot list is inline)
+constexpr int FBW = 16;   // largest band radius with a specialised kernel
 
 template <class R>
 struct Vec16;
@@ -67,6 +69,35 @@ struct FineShape {
     static_assert(HWL % VEC == 0 && VWL % VEC == 0, "whole vector windows");
     static_assert(2 * RY <= FT, "one horizontal item per thread");
     static_assert((FY / VWO) * FX == FT, "one vertical item per thread");
+};
+
+// Everything one launch reads from its kernel arguments, packed into a few
+// scalar-cache lines so that they arrive in one batch (the general argument
+// block spreads them over a kilobyte, and the compiler fetches it line by
+// line between branches).
+template <class R>
+struct FineArgs {
+    const R* in;            // x of every slot
+    R* out;                 // x + d
+    R* d;                   // Chebyshev direction, in place
+    const R* f;             // right-hand side
+    const R* sc;            // stencil planes: centre, north, east
+    const R* sn;
+    const R* se;
+    const R* dv;            // diag G_v (nv), diag G_h (nh)
+    const R* dh;
+    const double* lam2;     // per slot
+    const double* cheb;     // per slot (c1, c2) of this step
+    const int* active;      // per slot, may be null
+    double* part;           // partial sums of f . out [slot][tile]
+    int nv, nh;
+    int wrapv, wraph, per, f_shared;
+    int cheb_stride, dot, part_stride;
+    int zslot[FZ];          // slot of grid z
+    // half tap rows plus centre (the Gram rows are symmetric), padded to the
+    // kernel's radius: entry k is the coefficient at offset k - BW
+    R tv[FBW + 1];
+    R th[FBW + 1];
 };
 
 // Position x in [-n, 2n) of an axis of length n under the band's index map:
@@ -129,7 +160,7 @@ __device__ __forceinline__ void lds_window(const R* p, R (&w)[N]) {
 
 template <class R, int BW>
 __global__ void __launch_bounds__(FT)
-k_smooth_fine(ApplyArgsT<R> a) {
+k_smooth_fine(FineArgs<R> a) {
     using S = FineShape<R, BW>;
     using V = typename Vec16<R>::T;
     extern __shared__ __align__(16) double lds_raw[];
@@ -138,13 +169,31 @@ k_smooth_fine(ApplyArgsT<R> a) {
     R* ht = vin + S::RY * S::SX;                 // FX x SH, column-major
     const int t = threadIdx.x;
     const int z = blockIdx.z;
-    const int slot = z < a.zn ? a.zslot[z] : a.slots ? a.slots[z] : z;
-    const LevelGeomT<R>& g = a.g;
-    const int nv = g.nv, nh = g.nh;
-    // XCD-aware tile order, as in the general kernel
-    const int ntx = gridDim.x, nty = gridDim.y, ntile = ntx * nty;
-    int tile = blockIdx.x + ntx * blockIdx.y;
-    if ((ntile & 7) == 0) tile = (tile & 7) * (ntile >> 3) + (tile >> 3);
+    // no branch may precede the argument loads (the compiler would fetch
+    // the rest of the block after it): the slot list is always inline, and
+    // the XCD-aware tile order of the general kernel is selected by a mask
+    const int slot = a.zslot[z & (FZ - 1)];
+    const int nv = a.nv, nh = a.nh;
+    // An empty statement that takes arguments the vector loads need: the
+    // scalar loads of the argument block issue before it, then one wait.
+    // To the compiler it stands for a memory write, so the per-slot values
+    // read below become vector loads: those complete in order, and waiting
+    // for them does not wait for other scalar loads.
+    R tv[BW + 1], th[BW + 1];
+#pragma unroll
+    for (int k = 0; k <= BW; ++k) {
+        tv[k] = a.tv[k];
+        th[k] = a.th[k];
+    }
+    asm volatile("" ::"s"(a.in), "s"(a.sc), "s"(slot), "s"(nv));
+    const R l2 = (R)a.lam2[slot];
+    const R cd = (R)a.cheb[(size_t)slot * a.cheb_stride];
+    const R cr = (R)a.cheb[(size_t)slot * a.cheb_stride + 1];
+    const int ntx = nv / FY, nty = nh / FX, ntile = ntx * nty;   // the grid
+    const int tlin = blockIdx.x + ntx * blockIdx.y;
+    const int keep = -(int)((ntile & 7) != 0);
+    const int tile = (tlin & keep) |
+                     (((tlin & 7) * (ntile >> 3) + (tlin >> 3)) & ~keep);
     const int tx = tile % ntx, ty = tile / ntx;
     const int i0 = tx * FY, j0 = ty * FX;
     const size_t so = (size_t)slot * ((size_t)nv * nh);
@@ -152,8 +201,8 @@ k_smooth_fine(ApplyArgsT<R> a) {
     const R* f = a.f_shared ? a.f : a.f + so;
     R* dir = a.d + so;
     R* out = a.out + so;
-    const bool wrapv = g.gv.map == MAP_WRAP, wraph = g.gh.map == MAP_WRAP;
-    const int per = g.S.periodic;
+    const bool wrapv = a.wrapv, wraph = a.wraph;
+    const int per = a.per;
 
     // 1. operands of this thread's four outputs (rows r0..r0+3 of column c),
     //    requested first: right-hand side, direction, diagonals, couplings.
@@ -163,58 +212,71 @@ k_smooth_fine(ApplyArgsT<R> a) {
     R pf[4], pd[4], psc[4], psn[4], pse[4], psw[4], dgv[4];
     ld4(f, p0, pf);
     ld4((const R*)dir, p0, pd);
-    ld4(g.S.c, p0, psc);
-    ld4(g.S.cn, p0, psn);
-    ld4(g.S.ce, p0, pse);
-    ld4(g.gv.diag, (uint32_t)gi0, dgv);
-    const R dgh = g.gh.diag[gj];
+    ld4(a.sc, p0, psc);
+    ld4(a.sn, p0, psn);
+    ld4(a.se, p0, pse);
+    ld4(a.dv, (uint32_t)gi0, dgv);
+    const R dgh = a.dh[gj];
     // south coupling of the first row (the north coupling one row down) and
     // west couplings (the east couplings one column left): wrapped on a
     // periodic grid, zero across a non-periodic edge
     R pss0 = R(0);
-    if (gi0 > 0) pss0 = ldg(g.S.cn, p0 - 1);
-    else if (per) pss0 = ldg(g.S.cn, (uint32_t)(nv - 1) + (uint32_t)nv * gj);
+    if (gi0 > 0) pss0 = ldg(a.sn, p0 - 1);
+    else if (per) pss0 = ldg(a.sn, (uint32_t)(nv - 1) + (uint32_t)nv * gj);
     if (gj > 0) {
-        ld4(g.S.ce, p0 - (uint32_t)nv, psw);
+        ld4(a.se, p0 - (uint32_t)nv, psw);
     } else if (per) {
-        ld4(g.S.ce, (uint32_t)gi0 + (uint32_t)nv * (uint32_t)(nh - 1), psw);
+        ld4(a.se, (uint32_t)gi0 + (uint32_t)nv * (uint32_t)(nh - 1), psw);
     } else {
 #pragma unroll
         for (int o = 0; o < 4; ++o) psw[o] = R(0);
     }
 
     // 2. the tile plus its halo of BW rows and columns, as units of VEC
-    //    consecutive columns of one row, all loads in flight at once
+    //    consecutive columns of one row, all loads in flight at once.  Unit
+    //    e = t + FT k sits at row ii = e mod RY, column VEC (e div RY);
+    //    interior tiles need no index map.
     R u[S::UPT][S::VEC];
+    const bool inner = i0 >= BW && i0 + FY + BW <= nv && j0 >= BW &&
+                       j0 + FX + BW <= nh;
+    int ii = t % S::RY, jq = t / S::RY;
+    constexpr int DI = FT % S::RY, DJ = FT / S::RY;
+    if (inner) {
+        const R* sb = src + (size_t)(i0 - BW) + (size_t)nv * (size_t)(j0 - BW);
 #pragma unroll
-    for (int k = 0; k < S::UPT; ++k) {
-        const int e = t + FT * k;
+        for (int k = 0; k < S::UPT; ++k) {
+            const uint32_t o = (uint32_t)ii + (uint32_t)nv * (uint32_t)(jq * S::VEC);
 #pragma unroll
-        for (int cc = 0; cc < S::VEC; ++cc) u[k][cc] = R(0);
-        if (e < S::NU) {
-            const int ii = e % S::RY, jq = e / S::RY;
+            for (int cc = 0; cc < S::VEC; ++cc)
+                u[k][cc] = t + FT * k < S::NU
+                               ? ldg(sb, o + (uint32_t)nv * (uint32_t)cc)
+                               : R(0);
+            ii += DI;
+            jq += DJ;
+            if (ii >= S::RY) { ii -= S::RY; ++jq; }
+        }
+    } else {
+#pragma unroll
+        for (int k = 0; k < S::UPT; ++k) {
             const uint32_t gi = (uint32_t)fine_map(i0 - BW + ii, nv, wrapv);
 #pragma unroll
             for (int cc = 0; cc < S::VEC; ++cc) {
-                const int gjj = fine_map(j0 - BW + jq * S::VEC + cc, nh, wraph);
-                u[k][cc] = ldg(src, gi + (uint32_t)nv * (uint32_t)gjj);
+                u[k][cc] = R(0);
+                if (t + FT * k < S::NU) {
+                    const int gjj =
+                        fine_map(j0 - BW + jq * S::VEC + cc, nh, wraph);
+                    u[k][cc] = ldg(src, gi + (uint32_t)nv * (uint32_t)gjj);
+                }
             }
+            ii += DI;
+            jq += DJ;
+            if (ii >= S::RY) { ii -= S::RY; ++jq; }
         }
     }
-    // uniform taps, half row plus centre (the Gram rows are symmetric);
-    // positions beyond a direction's own radius are zero
-    R tv[BW + 1], th[BW + 1];
-#pragma unroll
-    for (int k = 0; k <= BW; ++k) {
-        const int kv = k - (BW - g.gv.bw), kh = k - (BW - g.gh.bw);
-        tv[k] = kv >= 0 ? g.gv.taps[kv] : R(0);
-        th[k] = kh >= 0 ? g.gh.taps[kh] : R(0);
-    }
-    const R l2 = (R)a.lam2[slot];
-    const R cd = (R)a.cheb[(size_t)slot * a.cheb_stride];
-    const R cr = (R)a.cheb[(size_t)slot * a.cheb_stride + 1];
-    // a slot that stopped inside a replayed chunk is skipped (its loads
-    // above are harmless, its stores are not)
+    // A slot that stopped inside a replayed chunk is skipped (its loads
+    // above are harmless, its stores are not).  The flag's load queues
+    // behind the tile loads, so waiting for it costs no more than the wait
+    // for the tile that follows anyway.
     if (a.active && !a.active[slot]) return;
 #pragma unroll
     for (int k = 0; k < S::UPT; ++k) {
@@ -308,6 +370,9 @@ int fine_radius(const ApplyArgsT<R>& a) {
     if (g.gv.map == MAP_ZERO || g.gh.map == MAP_ZERO) return -1;
     if (g.nv % FY != 0 || g.nh % FX != 0) return -1;
     if (!a.in || !a.out || !a.d || !a.f || !a.cheb || !a.lam2) return -1;
+    if (!g.gv.htaps || !g.gh.htaps) return -1;
+    // the slot of grid z comes from the inline list or is z itself
+    if (a.nslot > FZ || (a.slots && a.zn != a.nslot)) return -1;
     const void* ptrs[] = {a.in, a.out, a.d, a.f, g.S.c, g.S.cn, g.S.ce,
                           g.gv.diag};
     for (const void* p : ptrs)
@@ -315,7 +380,43 @@ int fine_radius(const ApplyArgsT<R>& a) {
     int bw = g.gv.bw > g.gh.bw ? g.gv.bw : g.gh.bw;
     bw += bw & 1;
     if (bw < 2) bw = 2;
-    return bw <= 16 ? bw : -1;
+    return bw <= FBW ? bw : -1;
+}
+
+template <class R>
+FineArgs<R> fine_args(const ApplyArgsT<R>& a, int bw) {
+    const LevelGeomT<R>& g = a.g;
+    FineArgs<R> f{};
+    f.in = a.in;
+    f.out = a.out;
+    f.d = a.d;
+    f.f = a.f;
+    f.sc = g.S.c;
+    f.sn = g.S.cn;
+    f.se = g.S.ce;
+    f.dv = g.gv.diag;
+    f.dh = g.gh.diag;
+    for (int k = 0; k <= FBW; ++k) {
+        const int kv = k - (bw - g.gv.bw), kh = k - (bw - g.gh.bw);
+        f.tv[k] = k <= bw && kv >= 0 ? g.gv.htaps[kv] : R(0);
+        f.th[k] = k <= bw && kh >= 0 ? g.gh.htaps[kh] : R(0);
+    }
+    f.lam2 = a.lam2;
+    f.cheb = a.cheb;
+    f.active = a.active;
+    f.part = a.part;
+    f.nv = g.nv;
+    f.nh = g.nh;
+    f.wrapv = g.gv.map == MAP_WRAP;
+    f.wraph = g.gh.map == MAP_WRAP;
+    f.per = g.S.periodic;
+    f.f_shared = a.f_shared;
+    f.cheb_stride = a.cheb_stride;
+    f.dot = a.dot;
+    f.part_stride = a.part_stride;
+    for (int i = 0; i < FZ; ++i)
+        f.zslot[i] = i < a.zn ? a.zslot[i] : i < a.nslot ? i : 0;
+    return f;
 }
 
 template <class R, int BW>
@@ -323,7 +424,7 @@ void launch_fine(const ApplyArgsT<R>& a, hipStream_t s) {
     using Sh = FineShape<R, BW>;
     dim3 grid(a.g.nv / FY, a.g.nh / FX, a.nslot);
     hipLaunchKernelGGL((k_smooth_fine<R, BW>), grid, dim3(FT), Sh::lds_bytes, s,
-                       a);
+                       fine_args(a, BW));
 }
 
 template <class R>

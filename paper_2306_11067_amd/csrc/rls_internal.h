@@ -29,6 +29,9 @@ struct BandDevT {
     const R* table = nullptr;   // n * (2bw+1)
     const R* diag = nullptr;    // n
     const R* rowabs = nullptr;  // n: sum_k |row r|
+    // host copy of the uniform row (2bw+1 values; host code only), for
+    // kernels that take the taps in their arguments
+    const R* htaps = nullptr;
 };
 
 // Galerkin stencil of L^T D^2 L on one level, five planes of n values:
