@@ -208,21 +208,6 @@ void launch_cholesky_inverse(double* Kc, int n, int nslot, double* work,
 void launch_check_weights(const double* d, int64_t n, int* bad,
                           hipStream_t s);
 
-// ---- vector / multigrid kernels (k_vec.hip) -------------------------
-void launch_jacobi_init(const LevelGeom& g, int nslot, const double* lam2,
-                        const int* slots, const int* active, const double* f,
-                        int f_shared, const double* cheb, int cheb_stride,
-                        double* x, double* d, hipStream_t s);
-void launch_restrict(const LevelGeom& fine, const LevelGeom& coarse, int nslot,
-                     const int* active, const double* res, double* fc,
-                     hipStream_t s);
-void launch_prolong_add(const LevelGeom& fine, const LevelGeom& coarse,
-                        int nslot, const int* active, const double* ec,
-                        double* x, hipStream_t s);
-void launch_coarse_solve(const double* Kinv, int n, int nslot,
-                         const int* slots, const int* active, const double* f,
-                         double* z, hipStream_t s);
-
 // ---- PCG kernels (k_pcg.hip) ------------------------------------------
 
 int vec_blocks(int64_t n);  // partial-sum slots per vector
