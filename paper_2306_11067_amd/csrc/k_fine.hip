@@ -62,8 +62,9 @@ struct FineShape {
     static constexpr int UPT = (NU + FT - 1) / FT;    // units per thread
     static constexpr int HWL = HWO + 2 * BW;          // horizontal window
     static constexpr int VWL = VWO + 2 * BW;          // vertical window
+    // input tile, horizontal-pass result, diag G_v of the tile's rows
     static constexpr size_t lds_bytes =
-        sizeof(R) * ((size_t)RY * SX + (size_t)FX * SH);
+        sizeof(R) * ((size_t)RY * SX + (size_t)FX * SH + FY);
     static_assert(BW % 2 == 0, "even band radius");
     static_assert(CX % VEC == 0, "whole load units per row");
     static_assert(HWL % VEC == 0 && VWL % VEC == 0, "whole vector windows");
@@ -81,8 +82,7 @@ struct FineArgs {
     R* out;                 // x + d
     R* d;                   // Chebyshev direction, in place
     const R* f;             // right-hand side
-    const R* sc;            // stencil planes: centre, north, east
-    const R* sn;
+    const R* sn;            // stencil planes: north, east couplings
     const R* se;
     const R* dv;            // diag G_v (nv), diag G_h (nh)
     const R* dh;
@@ -158,6 +158,29 @@ __device__ __forceinline__ void lds_window(const R* p, R (&w)[N]) {
     }
 }
 
+// The value of lane l - 1 of the same row of 16 lanes (DPP row shift; lane
+// 0 of a row receives zero).
+__device__ __forceinline__ int row_shr1_i(int v) {
+    return __builtin_amdgcn_update_dpp(0, v, 0x111, 0xf, 0xf, false);
+}
+__device__ __forceinline__ double row_shr1(double v) {
+    const long long b = __double_as_longlong(v);
+    const int lo = row_shr1_i((int)(b & 0xffffffffLL));
+    const int hi = row_shr1_i((int)(b >> 32));
+    return __longlong_as_double(((long long)hi << 32) |
+                                (long long)(unsigned)lo);
+}
+__device__ __forceinline__ float row_shr1(float v) {
+    return __int_as_float(row_shr1_i(__float_as_int(v)));
+}
+// The value of lane l - 16 of the wave (lanes 0..15 receive their own).
+__device__ __forceinline__ double shfl_up16(double v) {
+    return __shfl_up(v, 16, 64);
+}
+__device__ __forceinline__ float shfl_up16(float v) {
+    return __shfl_up(v, 16, 64);
+}
+
 template <class R, int BW>
 __global__ void __launch_bounds__(FT)
 k_smooth_fine(FineArgs<R> a) {
@@ -167,6 +190,7 @@ k_smooth_fine(FineArgs<R> a) {
     __shared__ double red[FT];
     R* vin = reinterpret_cast<R*>(lds_raw);      // RY x SX, row-major
     R* ht = vin + S::RY * S::SX;                 // FX x SH, column-major
+    R* dgl = ht + FX * S::SH;                    // FY: diag G_v, rows i0..
     const int t = threadIdx.x;
     const int z = blockIdx.z;
     // no branch may precede the argument loads (the compiler would fetch
@@ -185,7 +209,7 @@ k_smooth_fine(FineArgs<R> a) {
         tv[k] = a.tv[k];
         th[k] = a.th[k];
     }
-    asm volatile("" ::"s"(a.in), "s"(a.sc), "s"(slot), "s"(nv));
+    asm volatile("" ::"s"(a.in), "s"(a.sn), "s"(slot), "s"(nv));
     const R l2 = (R)a.lam2[slot];
     const R cd = (R)a.cheb[(size_t)slot * a.cheb_stride];
     const R cr = (R)a.cheb[(size_t)slot * a.cheb_stride + 1];
@@ -209,28 +233,34 @@ k_smooth_fine(FineArgs<R> a) {
     const int c = t & (FX - 1), r0 = VWO * (t >> 4);
     const int gi0 = i0 + r0, gj = j0 + c;
     const uint32_t p0 = (uint32_t)gi0 + (uint32_t)nv * (uint32_t)gj;
-    R pf[4], pd[4], psc[4], psn[4], pse[4], psw[4], dgv[4];
+    // The centre coupling is not read: on the finest level the stencil is
+    // L^T D^2 L, whose rows sum to zero, so it is minus the sum of the four
+    // couplings.  The west couplings (east couplings one column left) come
+    // from the neighbouring lane, the south coupling of the first row (north
+    // coupling one row down) from the lane 16 below; only the lanes at the
+    // tile's left column and at a wave's first row group load them (wrapped
+    // on a periodic grid, zero across a non-periodic edge).  diag G_v of the
+    // tile's 64 rows is loaded once per tile into LDS.
+    const int lane = t & 63;
+    R pf[4], pd[4], psn[4], pse[4], psw[4], dgr[4];
     ld4(f, p0, pf);
     ld4((const R*)dir, p0, pd);
-    ld4(a.sc, p0, psc);
     ld4(a.sn, p0, psn);
     ld4(a.se, p0, pse);
-    ld4(a.dv, (uint32_t)gi0, dgv);
     const R dgh = a.dh[gj];
-    // south coupling of the first row (the north coupling one row down) and
-    // west couplings (the east couplings one column left): wrapped on a
-    // periodic grid, zero across a non-periodic edge
     R pss0 = R(0);
-    if (gi0 > 0) pss0 = ldg(a.sn, p0 - 1);
-    else if (per) pss0 = ldg(a.sn, (uint32_t)(nv - 1) + (uint32_t)nv * gj);
-    if (gj > 0) {
-        ld4(a.se, p0 - (uint32_t)nv, psw);
-    } else if (per) {
-        ld4(a.se, (uint32_t)gi0 + (uint32_t)nv * (uint32_t)(nh - 1), psw);
-    } else {
 #pragma unroll
-        for (int o = 0; o < 4; ++o) psw[o] = R(0);
+    for (int o = 0; o < 4; ++o) psw[o] = dgr[o] = R(0);
+    if (lane < 16) {
+        if (gi0 > 0) pss0 = ldg(a.sn, p0 - 1);
+        else if (per) pss0 = ldg(a.sn, (uint32_t)(nv - 1) + (uint32_t)nv * gj);
     }
+    if (c == 0) {
+        if (gj > 0) ld4(a.se, p0 - (uint32_t)nv, psw);
+        else if (per)
+            ld4(a.se, (uint32_t)gi0 + (uint32_t)nv * (uint32_t)(nh - 1), psw);
+    }
+    if (t < FY / 4) ld4(a.dv, (uint32_t)(i0 + 4 * t), dgr);
 
     // 2. the tile plus its halo of BW rows and columns, as units of VEC
     //    consecutive columns of one row, all loads in flight at once.  Unit
@@ -278,6 +308,10 @@ k_smooth_fine(FineArgs<R> a) {
     // behind the tile loads, so waiting for it costs no more than the wait
     // for the tile that follows anyway.
     if (a.active && !a.active[slot]) return;
+    if (t < FY / 4) {
+#pragma unroll
+        for (int o = 0; o < 4; ++o) dgl[4 * t + o] = dgr[o];
+    }
 #pragma unroll
     for (int k = 0; k < S::UPT; ++k) {
         const int e = t + FT * k;
@@ -334,19 +368,29 @@ k_smooth_fine(FineArgs<R> a) {
     R colv[VWO + 2];
 #pragma unroll
     for (int o = 0; o < VWO + 2; ++o) colv[o] = vc[(o - 1) * S::SX];
+    {
+        const R up = shfl_up16(psn[VWO - 1]);
+        if (lane >= 16) pss0 = up;
+#pragma unroll
+        for (int o = 0; o < VWO; ++o) {
+            const R left = row_shr1(pse[o]);
+            if (c != 0) psw[o] = left;
+        }
+    }
     R nd[4], nx[4];
     double dot = 0.0;
 #pragma unroll
     for (int o = 0; o < VWO; ++o) {
         const R v = colv[o + 1];
         const R ss = o == 0 ? pss0 : psn[o - 1];
-        R sv = psc[o] * v;
+        const R sc = -(((psn[o] + ss) + pse[o]) + psw[o]);
+        R sv = sc * v;
         sv += psn[o] * colv[o + 2];
         sv += ss * colv[o];
         sv += pse[o] * vc[o * S::SX + 1];
         sv += psw[o] * vc[o * S::SX - 1];
         const R kvo = kv[o] + l2 * sv;
-        const R dg = dgv[o] * dgh + l2 * psc[o];
+        const R dg = dgl[r0 + o] * dgh + l2 * sc;
         nd[o] = cd * pd[o] + cr * (pf[o] - kvo) / dg;
         nx[o] = v + nd[o];
         dot += (double)pf[o] * (double)nx[o];
@@ -373,8 +417,7 @@ int fine_radius(const ApplyArgsT<R>& a) {
     if (!g.gv.htaps || !g.gh.htaps) return -1;
     // the slot of grid z comes from the inline list or is z itself
     if (a.nslot > FZ || (a.slots && a.zn != a.nslot)) return -1;
-    const void* ptrs[] = {a.in, a.out, a.d, a.f, g.S.c, g.S.cn, g.S.ce,
-                          g.gv.diag};
+    const void* ptrs[] = {a.in, a.out, a.d, a.f, g.S.cn, g.S.ce, g.gv.diag};
     for (const void* p : ptrs)
         if (!aligned16(p)) return -1;
     int bw = g.gv.bw > g.gh.bw ? g.gv.bw : g.gh.bw;
@@ -391,7 +434,6 @@ FineArgs<R> fine_args(const ApplyArgsT<R>& a, int bw) {
     f.out = a.out;
     f.d = a.d;
     f.f = a.f;
-    f.sc = g.S.c;
     f.sn = g.S.cn;
     f.se = g.S.ce;
     f.dv = g.gv.diag;
