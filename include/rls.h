@@ -80,9 +80,13 @@ typedef int rls_status;
  * Cholesky solve, which stay FP64.  An FP32 V-cycle is not exactly the same
  * linear map at every application, so PCG then uses the flexible
  * (Polak-Ribiere) beta; the attainable accuracy is that of the FP64
- * residual (Sec. 3, Algorithm 1 as the preconditioner of CG). */
+ * residual (Sec. 3, Algorithm 1 as the preconditioner of CG).
+ * MIXED_BF16: as MIXED_FP32, with the V-cycle's level vectors stored in
+ * BF16 (round to nearest even on every store; bands, stencils and all
+ * arithmetic FP32, coarse tail FP64).  Blur operators only. */
 #define RLS_PREC_FP64       0
 #define RLS_PREC_MIXED_FP32 1
+#define RLS_PREC_MIXED_BF16 2
 
 /* Tolerance semantics of rls_solve_sweep. */
 #define RLS_TOL_RELATIVE 0   /* ||A^T b - K x_i|| <= tol * ||A^T b||      */
@@ -121,7 +125,7 @@ typedef struct {
     double cheb_ratio;      /* finest-level smoothing interval
                                [rho/ratio, rho], rho the Gershgorin bound of
                                diag(K_k)^-1 K_k; > 1                         */
-    int precision;          /* RLS_PREC_FP64 or RLS_PREC_MIXED_FP32          */
+    int precision;          /* RLS_PREC_FP64, _MIXED_FP32 or _MIXED_BF16     */
     int nu_coarse;          /* same on the coarser levels (0: = nu), 1..256 */
     double cheb_ratio_coarse; /* same on the coarser levels (0: = cheb_ratio) */
 } rls_grid_desc;

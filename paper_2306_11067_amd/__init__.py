@@ -19,7 +19,8 @@ __all__ = ["Problem", "RLSError", "BC", "LBC"]
 BC = {"periodic": L.RLS_BC_PERIODIC, "reflective": L.RLS_BC_REFLECTIVE,
       "zero": L.RLS_BC_ZERO}
 LBC = {"neumann": L.RLS_L_NEUMANN, "periodic": L.RLS_L_PERIODIC}
-PREC = {"fp64": L.RLS_PREC_FP64, "mixed_fp32": L.RLS_PREC_MIXED_FP32}
+PREC = {"fp64": L.RLS_PREC_FP64, "mixed_fp32": L.RLS_PREC_MIXED_FP32,
+        "mixed_bf16": L.RLS_PREC_MIXED_BF16}
 
 
 class RLSError(RuntimeError):

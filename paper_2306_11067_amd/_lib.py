@@ -22,6 +22,7 @@ RLS_BC_PERIODIC, RLS_BC_REFLECTIVE, RLS_BC_ZERO = 0, 1, 2
 RLS_L_NEUMANN, RLS_L_PERIODIC = 0, 1
 RLS_PREC_FP64 = 0
 RLS_PREC_MIXED_FP32 = 1
+RLS_PREC_MIXED_BF16 = 2
 RLS_TOL_RELATIVE, RLS_TOL_ABSOLUTE = 0, 1
 RLS_FLAG_CONVERGED, RLS_FLAG_MAXIT = 1, 2
 RLS_FLAG_BREAKDOWN, RLS_FLAG_NONFINITE = 4, 8

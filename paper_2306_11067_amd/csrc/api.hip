@@ -215,9 +215,10 @@ struct Work {
     DBuf fpart, rrpart, outv, slots;
     DBuf part_pq, part_rr, part_rz;    // PCG partial sums per slot
     DBuf part_zq;                      // flexible beta: partials of z . q
-    DBuf r32, z32;                     // FP32 V-cycle: fine rhs and result
+    // reduced-precision V-cycle (FP32 or BF16 elements): fine rhs, result
+    DBuf rlo, zlo;
     DBuf ctv, cty, ctt, ctres, ctv32, cty32, ctt32, ctres32;  // sparse levels
-    std::vector<DBuf> lx32, lxb32, ld32, lf32;   // FP32 level vectors
+    std::vector<DBuf> lxlo, lxblo, ldlo, lflo;   // its level vectors
     int* h_active = nullptr;     // pinned host mirrors
     int* h_slots = nullptr;
     ~Work() {
@@ -314,10 +315,14 @@ void run_begin(rls_problem* P, hipStream_t s) {
 }
 
 // The level operator of either operator kind.
-template <class R>
-void level_apply(int pro, int epi, const ApplyArgsT<R>& a, hipStream_t s) {
-    if (a.g.ct.on) launch_ct_apply(pro, epi, a, s);
-    else launch_apply(pro, epi, a, s);
+template <class R, class V>
+void level_apply(int pro, int epi, const ApplyArgsT<R, V>& a, hipStream_t s) {
+    if constexpr (std::is_same<V, bf16>::value) {
+        launch_apply(pro, epi, a, s);   // sparse operators have no BF16 path
+    } else {
+        if (a.g.ct.on) launch_ct_apply(pro, epi, a, s);
+        else launch_apply(pro, epi, a, s);
+    }
 }
 
 void smooth_fine(rls_problem* P, const ApplyArgs& a, hipStream_t s) {
@@ -329,10 +334,16 @@ void smooth_fine(rls_problem* P, const ApplyArgs& a, hipStream_t s) {
     else launch_smooth_fine(a, s);
     if (P->timer_on) P->run_cur.launches += 1;
 }
-// FP32 V-cycle: not timed (the kernel timer covers the FP64 step).
+// FP32 and BF16 V-cycles: not timed (the kernel timer covers the FP64
+// step).
 void smooth_fine(rls_problem* P, const ApplyArgsT<float>& a, hipStream_t s) {
     if (a.g.ct.on) launch_ct_apply(PRO_PLAIN, EPI_CHEB, a, s);
     else if (P->fine_generic) launch_apply(PRO_PLAIN, EPI_CHEB, a, s);
+    else launch_smooth_fine(a, s);
+}
+void smooth_fine(rls_problem* P, const ApplyArgsT<float, bf16>& a,
+                 hipStream_t s) {
+    if (P->fine_generic) launch_apply(PRO_PLAIN, EPI_CHEB, a, s);
     else launch_smooth_fine(a, s);
 }
 
@@ -431,17 +442,19 @@ rls_status ensure_work(rls_problem* P, int nslot) {
             Lv.ct.res32 = w.ctres32.as<float>();
         }
     }
-    if (P->prec == RLS_PREC_MIXED_FP32) {
-        RLS_TRY(dalloc(w.r32, sizeof(float) * (size_t)cap * n));
-        RLS_TRY(dalloc(w.z32, sizeof(float) * (size_t)cap * n));
-        for (auto* v : {&w.lx32, &w.lxb32, &w.ld32, &w.lf32}) v->resize(L);
+    if (P->prec != RLS_PREC_FP64) {
+        const size_t esz = P->prec == RLS_PREC_MIXED_BF16 ? sizeof(bf16)
+                                                          : sizeof(float);
+        RLS_TRY(dalloc(w.rlo, esz * (size_t)cap * n));
+        RLS_TRY(dalloc(w.zlo, esz * (size_t)cap * n));
+        for (auto* v : {&w.lxlo, &w.lxblo, &w.ldlo, &w.lflo}) v->resize(L);
         for (int k = 0; k < L; ++k) {
-            const size_t bytes = sizeof(float) * (size_t)cap * P->lev[k].n();
-            RLS_TRY(dalloc(w.lxb32[k], bytes));
-            RLS_TRY(dalloc(w.ld32[k], bytes));
+            const size_t bytes = esz * (size_t)cap * P->lev[k].n();
+            RLS_TRY(dalloc(w.lxblo[k], bytes));
+            RLS_TRY(dalloc(w.ldlo[k], bytes));
             if (k > 0) {
-                RLS_TRY(dalloc(w.lx32[k], bytes));
-                RLS_TRY(dalloc(w.lf32[k], bytes));
+                RLS_TRY(dalloc(w.lxlo[k], bytes));
+                RLS_TRY(dalloc(w.lflo[k], bytes));
             }
         }
     }
@@ -531,7 +544,7 @@ rls_status build_direction(rls_problem* P, const std::vector<double>& taps,
             RLS_HIP(hipStreamSynchronize(s));
             G.htaps32.assign(G.htaps.begin(), G.htaps.end());
         }
-        if (P->prec == RLS_PREC_MIXED_FP32) {
+        if (P->prec != RLS_PREC_FP64) {   // FP32 copies for the V-cycle
             const size_t tn = (size_t)nk * (2 * bw + 1);
             RLS_TRY(dalloc(G.table32, sizeof(float) * tn));
             RLS_TRY(dalloc(G.diag32, sizeof(float) * nk));
@@ -692,7 +705,7 @@ rls_status install_weights(rls_problem* P, const double* d, hipStream_t s) {
                                     P->periodic, L.planes.as<double>(), s);
         launch_stencil_rowabs(L.planes.as<double>(), L.nv, L.nh, P->periodic,
                               L.srowabs.as<double>(), s);
-        if (P->prec == RLS_PREC_MIXED_FP32) {
+        if (P->prec != RLS_PREC_FP64) {   // FP32 copies for the V-cycle
             RLS_TRY(dalloc(L.planes32, sizeof(float) * 5 * m));
             launch_to_f32(L.planes.as<double>(), 5 * m, 1, nullptr,
                           L.planes32.as<float>(), s);
@@ -779,8 +792,8 @@ struct CycleCtl {
 
 // Put the slot list in the kernel arguments when it is the sweep's list
 // and short enough.
-template <class R>
-static void inline_slots(const rls_problem* P, ApplyArgsT<R>& a) {
+template <class R, class V>
+static void inline_slots(const rls_problem* P, ApplyArgsT<R, V>& a) {
     a.zn = 0;
     if (!a.slots || a.slots != P->w.slots.as<int>() || !P->hslots ||
         P->hslots_n != a.nslot || a.nslot > ZINLINE)
@@ -791,30 +804,36 @@ static void inline_slots(const rls_problem* P, ApplyArgsT<R>& a) {
 
 // z = V-cycle(f) on level k (Algorithm 1, gamma = 1, V(nu, nu)), for the
 // nslot slots listed in `slots` (null: slots 0..nslot-1).
-template <class R>
-R* lvec(std::vector<DBuf>& v64, std::vector<DBuf>& v32, int k);
+template <class V>
+V* lvec(std::vector<DBuf>& v64, std::vector<DBuf>& vlo, int k);
 template <>
 double* lvec<double>(std::vector<DBuf>& v64, std::vector<DBuf>&, int k) {
     return v64[k].as<double>();
 }
 template <>
-float* lvec<float>(std::vector<DBuf>&, std::vector<DBuf>& v32, int k) {
-    return v32[k].as<float>();
+float* lvec<float>(std::vector<DBuf>&, std::vector<DBuf>& vlo, int k) {
+    return vlo[k].as<float>();
+}
+template <>
+bf16* lvec<bf16>(std::vector<DBuf>&, std::vector<DBuf>& vlo, int k) {
+    return vlo[k].as<bf16>();
 }
 
-// R is the V-cycle's value type (double, or float under flexible PCG); the
+// V is the V-cycle's vector type (double, or float or bf16 under flexible
+// PCG), R its arithmetic type (double, float for both reduced types); the
 // coarse tail always computes in FP64.
-template <class R>
+template <class V>
 void vcycle(rls_problem* P, int k, int nslot, const int* slots,
-            const int* active, const R* f, R* z, const CycleCtl& ctl,
+            const int* active, const V* f, V* z, const CycleCtl& ctl,
             hipStream_t s) {
+    using R = typename CompOf<V>::T;
     Work& w = P->w;
     const int L = P->levels;
     const int cs = 2 * P->nu_max;
     const int nu = P->nu[k];
     const bool top = k == 0;
     if (k >= P->kt) {
-        TailArgsT<R> t;
+        TailArgsT<V> t;
         t.nlev = L - k;
         for (int i = 0; i < t.nlev; ++i) {
             const LevelGeom g = P->lev[k + i].geom();
@@ -851,8 +870,8 @@ void vcycle(rls_problem* P, int k, int nslot, const int* slots,
     constexpr bool TIMED = std::is_same<R, double>::value;
     const LevelGeomT<R> g = P->lev[k].template geom_t<R>();
     const double* cheb = w.cheb.as<double>() + (size_t)k * w.cap * cs;
-    R* d = lvec<R>(w.ld, w.ld32, k);
-    ApplyArgsT<R> a;
+    V* d = lvec<V>(w.ld, w.ldlo, k);
+    ApplyArgsT<R, V> a;
     a.g = g;
     a.nslot = nslot;
     a.slots = slots;
@@ -863,7 +882,7 @@ void vcycle(rls_problem* P, int k, int nslot, const int* slots,
     a.cheb_stride = cs;
     a.cheb_first = cheb;
     inline_slots(P, a);
-    auto gate_first = [&](ApplyArgsT<R>& aa) {
+    auto gate_first = [&](ApplyArgsT<R, V>& aa) {
         if (top && ctl.gate) {
             aa.gate = 1;
             aa.st = ctl.st;
@@ -872,17 +891,17 @@ void vcycle(rls_problem* P, int k, int nslot, const int* slots,
             aa.nrr = ctl.nrr;
         }
     };
-    R* fc = lvec<R>(w.lf, w.lf32, k + 1);
-    R* zc = lvec<R>(w.lx, w.lx32, k + 1);
+    V* fc = lvec<V>(w.lf, w.lflo, k + 1);
+    V* zc = lvec<V>(w.lx, w.lxlo, k + 1);
     if (nu == 1) {
         // x1 = c f / diag never leaves the tiles: the restriction kernel
         // forms it on the fly, the correction kernel forms it again.
-        ApplyArgsT<R> r = a;
+        ApplyArgsT<R, V> r = a;
         gate_first(r);
         r.fc = fc;
         level_apply(PRO_JACOBI, EPI_RESTRICT, r, s);
-        vcycle(P, k + 1, nslot, slots, active, (const R*)fc, zc, CycleCtl(), s);
-        ApplyArgsT<R> c = a;
+        vcycle(P, k + 1, nslot, slots, active, (const V*)fc, zc, CycleCtl(), s);
+        ApplyArgsT<R, V> c = a;
         c.ec = zc;
         c.out = z;
         c.cheb = cheb;
@@ -898,12 +917,12 @@ void vcycle(rls_problem* P, int k, int nslot, const int* slots,
     // nu - 2 more pre steps and nu post steps each swap; choose buffer 0 so
     // that the result lands in z.
     const int swaps = (nu - 2) + nu;
-    R* bufs[2];
+    V* bufs[2];
     bufs[swaps % 2 == 0 ? 0 : 1] = z;
-    bufs[swaps % 2 == 0 ? 1 : 0] = lvec<R>(w.lxb, w.lxb32, k);
+    bufs[swaps % 2 == 0 ? 1 : 0] = lvec<V>(w.lxb, w.lxblo, k);
     int cur = 0;
     {
-        ApplyArgsT<R> j = a;
+        ApplyArgsT<R, V> j = a;
         gate_first(j);
         j.out = bufs[cur];
         j.cheb = cheb + 2;
@@ -911,7 +930,7 @@ void vcycle(rls_problem* P, int k, int nslot, const int* slots,
     }
     if (TIMED && top && nu > 2) run_begin(P, s);
     for (int st = 2; st < nu; ++st) {
-        ApplyArgsT<R> c = a;
+        ApplyArgsT<R, V> c = a;
         c.in = bufs[cur];
         c.out = bufs[1 - cur];
         c.cheb = cheb + 2 * st;
@@ -921,14 +940,14 @@ void vcycle(rls_problem* P, int k, int nslot, const int* slots,
     }
     if (TIMED && top && nu > 2) run_end(P, s);
     {
-        ApplyArgsT<R> r = a;                        // residual + restriction
+        ApplyArgsT<R, V> r = a;                     // residual + restriction
         r.in = bufs[cur];
         r.fc = fc;
         level_apply(PRO_PLAIN, EPI_RESTRICT, r, s);
     }
-    vcycle(P, k + 1, nslot, slots, active, (const R*)fc, zc, CycleCtl(), s);
+    vcycle(P, k + 1, nslot, slots, active, (const V*)fc, zc, CycleCtl(), s);
     for (int st = 0; st < nu; ++st) {              // correction + smoothing
-        ApplyArgsT<R> c = a;
+        ApplyArgsT<R, V> c = a;
         c.in = bufs[cur];
         c.out = bufs[1 - cur];
         c.cheb = cheb + 2 * st;
@@ -944,6 +963,35 @@ void vcycle(rls_problem* P, int k, int nslot, const int* slots,
         if (TIMED && top && st > 0 && st == nu - 1) run_end(P, s);
         cur = 1 - cur;
     }
+}
+
+// z = M r through the reduced-precision V-cycle with vectors of type V:
+// narrowing of r (after the convergence test when st is given), the
+// V-cycle, widening of z with the partials of r . z (and z . q).
+template <class V>
+void vcycle_lo_t(rls_problem* p, int ns, const int* sl, int* active,
+                 SlotState* st, const double* part_rr, int nrr, const double* r,
+                 double* z, const double* q, double* part_rz, double* part_zq,
+                 int npart, hipStream_t s) {
+    Work& w = p->w;
+    const int64_t n = p->n();
+    V* rlo = w.rlo.as<V>();
+    V* zlo = w.zlo.as<V>();
+    launch_vc_enter<V>(st, active, sl, ns, part_rr, nrr, n, r, rlo, s);
+    vcycle<V>(p, 0, ns, sl, active, (const V*)rlo, zlo, CycleCtl(), s);
+    launch_vc_exit<V>(sl, active, ns, n, npart, zlo, z, r, q, part_rz, part_zq,
+                      s);
+}
+void vcycle_lo(rls_problem* p, int ns, const int* sl, int* active,
+               SlotState* st, const double* part_rr, int nrr, const double* r,
+               double* z, const double* q, double* part_rz, double* part_zq,
+               int npart, hipStream_t s) {
+    if (p->prec == RLS_PREC_MIXED_BF16)
+        vcycle_lo_t<bf16>(p, ns, sl, active, st, part_rr, nrr, r, z, q, part_rz,
+                          part_zq, npart, s);
+    else
+        vcycle_lo_t<float>(p, ns, sl, active, st, part_rr, nrr, r, z, q,
+                           part_rz, part_zq, npart, s);
 }
 
 rls_status validate_grid(const rls_grid_desc* g) {
@@ -969,9 +1017,11 @@ rls_status validate_grid(const rls_grid_desc* g) {
     const int64_t nc = (int64_t)(g->nv >> (g->levels - 1)) * (g->nh >> (g->levels - 1));
     if (nc > 1024)
         return fail(RLS_E_ARG, "coarsest level exceeds 1024 unknowns; add levels");
-    if (g->precision != RLS_PREC_FP64 && g->precision != RLS_PREC_MIXED_FP32)
+    if (g->precision != RLS_PREC_FP64 && g->precision != RLS_PREC_MIXED_FP32 &&
+        g->precision != RLS_PREC_MIXED_BF16)
         return fail(RLS_E_UNSUPPORTED,
-                    "precision must be RLS_PREC_FP64 or RLS_PREC_MIXED_FP32");
+                    "precision must be RLS_PREC_FP64, RLS_PREC_MIXED_FP32 or "
+                    "RLS_PREC_MIXED_BF16");
     return RLS_OK;
 }
 
@@ -1273,15 +1323,10 @@ rls_status rls_vcycle(rls_problem* p, const double* lam, int nlam,
     RLS_TRY(ensure_work(p, nlam));
     RLS_TRY(upload_lam(p, lam, nlam, s));
     RLS_TRY(prepare_sweep(p, nlam, s));
-    if (p->prec == RLS_PREC_MIXED_FP32) {
-        Work& w = p->w;
-        const int64_t n = p->n();
-        launch_to_f32(r, n, nlam, nullptr, w.r32.as<float>(), s);
-        vcycle(p, 0, nlam, nullptr, nullptr, w.r32.as<float>(),
-               w.z32.as<float>(), CycleCtl(), s);
-        launch_vc_exit(nullptr, nullptr, nlam, n, apply_tiles(p->lev[0].geom()),
-                       w.z32.as<float>(), z, r, nullptr, w.part_rz.as<double>(),
-                       nullptr, s);
+    if (p->prec != RLS_PREC_FP64) {
+        vcycle_lo(p, nlam, nullptr, nullptr, nullptr, nullptr, 0, r, z, nullptr,
+                  p->w.part_rz.as<double>(), nullptr,
+                  apply_tiles(p->lev[0].geom()), s);
     } else {
         vcycle(p, 0, nlam, nullptr, nullptr, r, z, CycleCtl(), s);
     }
@@ -1414,14 +1459,10 @@ rls_status rls_solve_sweep(rls_problem* p, const double* b, const double* lam,
     launch_sumsq_slots(r, n, ns, rrpart, s);
     // z0 = M r0 with partial sums of r0 . z0 (consumed by the first
     // iteration, where beta = 0 makes p0 = z0)
-    const bool mixed = p->prec == RLS_PREC_MIXED_FP32;
+    const bool mixed = p->prec != RLS_PREC_FP64;
     if (mixed) {
-        float* r32 = w.r32.as<float>();
-        float* z32 = w.z32.as<float>();
-        launch_to_f32(r, n, ns, nullptr, r32, s);
-        vcycle(p, 0, ns, nullptr, nullptr, (const float*)r32, z32, CycleCtl(), s);
-        launch_vc_exit(nullptr, nullptr, ns, n, tiles0, z32, z, r, nullptr,
-                       w.part_rz.as<double>(), nullptr, s);
+        vcycle_lo(p, ns, nullptr, nullptr, nullptr, nullptr, 0, r, z, nullptr,
+                  w.part_rz.as<double>(), nullptr, tiles0, s);
     } else {
         CycleCtl c0;
         c0.dot_part = w.part_rz.as<double>();
@@ -1466,16 +1507,12 @@ rls_status rls_solve_sweep(rls_problem* p, const double* b, const double* lam,
                          w.part_pq.as<double>(), tiles0, cur,
                          w.part_rr.as<double>(), ss);
         if (mixed) {
-            // FP32 V-cycle: gate and narrowing, V-cycle, widening with the
-            // partials of r . z and z . q for the flexible beta
-            float* r32 = w.r32.as<float>();
-            float* z32 = w.z32.as<float>();
-            launch_vc_enter(st, active, sl, nact, w.part_rr.as<double>(), vb, n,
-                            r, r32, ss);
-            vcycle(p, 0, nact, sl, active, (const float*)r32, z32, CycleCtl(),
-                   ss);
-            launch_vc_exit(sl, active, nact, n, tiles0, z32, z, r, q,
-                           w.part_rz.as<double>(), w.part_zq.as<double>(), ss);
+            // reduced-precision V-cycle: gate and narrowing, V-cycle,
+            // widening with the partials of r . z and z . q for the
+            // flexible beta
+            vcycle_lo(p, nact, sl, active, st, w.part_rr.as<double>(), vb, r, z,
+                      q, w.part_rz.as<double>(), w.part_zq.as<double>(), tiles0,
+                      ss);
             return;
         }
         CycleCtl c;

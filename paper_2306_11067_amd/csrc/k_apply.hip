@@ -40,6 +40,15 @@ __device__ __forceinline__ void stu(R* base, uint32_t idx, R v) {
     *reinterpret_cast<R*>(reinterpret_cast<char*>(base) +
                           idx * (uint32_t)sizeof(R)) = v;
 }
+// Vector element in the arithmetic type R, stored as V.
+template <class R, class V>
+__device__ __forceinline__ R ldv(const V* base, uint32_t idx) {
+    return Cvt<R, V>::in(ldu(base, idx));
+}
+template <class R, class V>
+__device__ __forceinline__ void stv(V* base, uint32_t idx, R v) {
+    stu(base, idx, Cvt<R, V>::out(v));
+}
 
 template <class R>
 __device__ __forceinline__ R diag_at(const LevelGeomT<R>& g, R l2, int i,
@@ -61,8 +70,8 @@ __device__ __forceinline__ int interp_sources(int f, int nf, int periodic,
 }
 
 // (P e)(fi, fj) for the coarse vector e of size (nf_v/2) x (nf_h/2).
-template <class R>
-__device__ __forceinline__ R prolong_at(const R* __restrict__ e, int fi,
+template <class R, class V>
+__device__ __forceinline__ R prolong_at(const V* __restrict__ e, int fi,
                                         int fj, int nvf, int nhf,
                                         int periodic) {
     int Ii[2], Jj[2];
@@ -73,7 +82,8 @@ __device__ __forceinline__ R prolong_at(const R* __restrict__ e, int fi,
     R s = R(0);
     for (int b = 0; b < nj; ++b) {
         R cs = R(0);
-        for (int a = 0; a < ni; ++a) cs += wi[a] * e[Ii[a] + nvc * Jj[b]];
+        for (int a = 0; a < ni; ++a)
+            cs += wi[a] * Cvt<R, V>::in(e[Ii[a] + nvc * Jj[b]]);
         s += wj[b] * cs;
     }
     return s;
@@ -166,15 +176,15 @@ __device__ __forceinline__ bool out_index(int e, const TileShape& T,
     return true;
 }
 
-// The slot's arrays (uniform over the workgroup).
-template <class R>
+// The slot's arrays (uniform over the workgroup), V the storage type.
+template <class V>
 struct SlotPtrs {
-    const R* src;   // operand v (or z for the p update)
-    const R* pold;  // previous search direction
-    const R* f;     // right-hand side
-    R* d;           // Chebyshev direction
-    R* out;         // result
-    R* pnew;        // new search direction
+    const V* src;   // operand v (or z for the p update)
+    const V* pold;  // previous search direction
+    const V* f;     // right-hand side
+    V* d;           // Chebyshev direction
+    V* out;         // result
+    V* pnew;        // new search direction
 };
 
 // Operands of one output point from global memory, requested before the
@@ -186,10 +196,10 @@ struct OutPre {
     R f, d, sc, sn, ss, se, sw;
 };
 
-template <int PRO, int EPI, class R>
+template <int PRO, int EPI, class R, class V>
 __device__ __forceinline__ void out_load(OutPre<R>& q, int e,
-                                         const ApplyArgsT<R>& a,
-                                         const SlotPtrs<R>& sp,
+                                         const ApplyArgsT<R, V>& a,
+                                         const SlotPtrs<V>& sp,
                                          const TileShape& T, int i0, int j0) {
     const LevelGeomT<R>& g = a.g;
     const int nv = g.nv, nh = g.nh, per = g.S.periodic;
@@ -206,15 +216,15 @@ __device__ __forceinline__ void out_load(OutPre<R>& q, int e,
     q.se = ldu(g.S.ce, p);
     if (okjm) q.sw = ldu(g.S.ce, gi + (uint32_t)nv * jm);
     if (EPI == EPI_RESID || EPI == EPI_RESTRICT || EPI == EPI_CHEB)
-        q.f = ldu(sp.f, p);
-    if (EPI == EPI_CHEB && PRO != PRO_JACOBI) q.d = ldu(sp.d, p);
+        q.f = ldv<R>(sp.f, p);
+    if (EPI == EPI_CHEB && PRO != PRO_JACOBI) q.d = ldv<R>(sp.d, p);
 }
 
 // Stencil term and epilogue at output e; K v's Gram part is staged in kvs.
-template <int PRO, int EPI, class R>
+template <int PRO, int EPI, class R, class V>
 __device__ __forceinline__ void out_point(const OutPre<R>& q, int e,
-                                          const ApplyArgsT<R>& a,
-                                          const SlotPtrs<R>& sp,
+                                          const ApplyArgsT<R, V>& a,
+                                          const SlotPtrs<V>& sp,
                                           const TileShape& T, const R* vin,
                                           R* kvs, R l2, const R* dgl, R c0,
                                           R c1, int i0, int j0, double& dot) {
@@ -246,27 +256,27 @@ __device__ __forceinline__ void out_point(const OutPre<R>& q, int e,
     const R kv = kvs[c * T.SR + r] + l2 * sv;
     const R v = vc[0];
     if (EPI == EPI_STORE) {
-        stu(sp.out, p, kv);
+        stv(sp.out, p, kv);
     } else if (EPI == EPI_DOT) {
-        stu(sp.out, p, kv);
+        stv(sp.out, p, kv);
         dot += (double)v * (double)kv;
     } else if (EPI == EPI_RESID) {
-        stu(sp.out, p, q.f - kv);
+        stv(sp.out, p, q.f - kv);
     } else if (EPI == EPI_RESTRICT) {
         kvs[c * T.SR + r] = q.f - kv;
     } else {   // EPI_CHEB
         const R dg = dgl[r] * dgl[T.RO + c] + l2 * q.sc;
         const R dprev = PRO == PRO_JACOBI ? v : q.d;
         const R dn = c0 * dprev + c1 * (q.f - kv) / dg;
-        stu(sp.d, p, dn);
+        stv(sp.d, p, dn);
         const R xn = v + dn;
-        stu(sp.out, p, xn);
+        stv(sp.out, p, xn);
         if (a.dot) dot += (double)q.f * (double)xn;
     }
 }
 
-template <int PRO, int EPI, class R>
-__device__ __forceinline__ void apply_body(const ApplyArgsT<R>& a, R* lds,
+template <int PRO, int EPI, class R, class V>
+__device__ __forceinline__ void apply_body(const ApplyArgsT<R, V>& a, R* lds,
                                            double* red) {
     constexpr int EXT = EPI == EPI_RESTRICT ? 1 : 0;
     constexpr int NT = APPLY_THREADS;
@@ -298,7 +308,7 @@ __device__ __forceinline__ void apply_body(const ApplyArgsT<R>& a, R* lds,
     R* ch = cv + (size_t)T.NCV * T.WVP;
     R* dgl = ch + (size_t)T.NCH * T.WHP;   // diag G_v rows, diag G_h cols
     const size_t so = (size_t)slot * n;
-    SlotPtrs<R> sp;
+    SlotPtrs<V> sp;
     sp.src = a.in ? a.in + so : nullptr;
     sp.pold = a.pold ? a.pold + so : nullptr;
     sp.f = a.f ? (a.f_shared ? a.f : a.f + so) : nullptr;
@@ -371,28 +381,28 @@ __device__ __forceinline__ void apply_body(const ApplyArgsT<R>& a, R* lds,
                 if (rin && okv && jj < T.CX && okh) {
                     const uint32_t p = gi + (uint32_t)nv * gj;
                     if (PRO == PRO_PLAIN) {
-                        v[u] = ldu(sp.src, p);
+                        v[u] = ldv<R>(sp.src, p);
                     } else if (PRO == PRO_PUPDATE) {
                         // p_old is undefined before the first iteration
-                        const R po = beta == 0.0 ? R(0) : ldu(sp.pold, p);
-                        v[u] = ldu(sp.src, p) + (R)beta * po;
+                        const R po = beta == 0.0 ? R(0) : ldv<R>(sp.pold, p);
+                        v[u] = ldv<R>(sp.src, p) + (R)beta * po;
                     } else if (PRO == PRO_JACOBI) {
-                        v[u] = cj * ldu(sp.f, p) / diag_at(g, l2, gi, gj, p);
+                        v[u] = cj * ldv<R>(sp.f, p) / diag_at(g, l2, gi, gj, p);
                     } else if (PRO == PRO_PROLONG) {
-                        v[u] = ldu(sp.src, p) +
-                               prolong_at(a.ec + (size_t)slot * (n >> 2), gi, gj,
-                                          nv, nh, per);
+                        v[u] = ldv<R>(sp.src, p) +
+                               prolong_at<R>(a.ec + (size_t)slot * (n >> 2), gi,
+                                             gj, nv, nh, per);
                     } else {   // PRO_PROLONG_JAC
-                        v[u] = cj * ldu(sp.f, p) / diag_at(g, l2, gi, gj, p) +
-                               prolong_at(a.ec + (size_t)slot * (n >> 2), gi, gj,
-                                          nv, nh, per);
+                        v[u] = cj * ldv<R>(sp.f, p) / diag_at(g, l2, gi, gj, p) +
+                               prolong_at<R>(a.ec + (size_t)slot * (n >> 2), gi,
+                                             gj, nv, nh, per);
                     }
                 }
             }
             if (rb == 0 && cb == 0) {
 #pragma unroll
                 for (int k = 0; k < NPRE; ++k)
-                    out_load<PRO, EPI, R>(pre[k], t + k * NT, a, sp, T, i0, j0);
+                    out_load<PRO, EPI, R, V>(pre[k], t + k * NT, a, sp, T, i0, j0);
             }
 #pragma unroll
             for (int u = 0; u < LB; ++u) {
@@ -405,7 +415,7 @@ __device__ __forceinline__ void apply_body(const ApplyArgsT<R>& a, R* lds,
                         const bool own = ii >= T.hv && ii < T.hv + TILE_Y &&
                                          jj >= T.hh && jj < T.hh + TILE_X &&
                                          ui < nv && uj < nh;
-                        if (own) stu(sp.pnew, ui + (uint32_t)nv * uj, v[u]);
+                        if (own) stv(sp.pnew, ui + (uint32_t)nv * uj, v[u]);
                     }
                 }
             }
@@ -552,13 +562,13 @@ __device__ __forceinline__ void apply_body(const ApplyArgsT<R>& a, R* lds,
     const int nout = T.RO * T.CO;
 #pragma unroll
     for (int k = 0; k < NPRE; ++k)
-        out_point<PRO, EPI, R>(pre[k], t + k * NT, a, sp, T, vin, kvs, l2, dgl, c0,
-                            c1, i0, j0, dot);
+        out_point<PRO, EPI, R, V>(pre[k], t + k * NT, a, sp, T, vin, kvs, l2,
+                                  dgl, c0, c1, i0, j0, dot);
     for (int e = t + NPRE * NT; e < nout; e += NT) {
         OutPre<R> q;
-        out_load<PRO, EPI, R>(q, e, a, sp, T, i0, j0);
-        out_point<PRO, EPI, R>(q, e, a, sp, T, vin, kvs, l2, dgl, c0, c1, i0, j0,
-                            dot);
+        out_load<PRO, EPI, R, V>(q, e, a, sp, T, i0, j0);
+        out_point<PRO, EPI, R, V>(q, e, a, sp, T, vin, kvs, l2, dgl, c0, c1, i0,
+                                  j0, dot);
     }
 
     if (EPI == EPI_RESTRICT) {
@@ -589,7 +599,8 @@ __device__ __forceinline__ void apply_body(const ApplyArgsT<R>& a, R* lds,
                 }
                 s += wj * cs;
             }
-            a.fc[(size_t)slot * nvc * nhc + I + (int64_t)nvc * J] = s;
+            a.fc[(size_t)slot * nvc * nhc + I + (int64_t)nvc * J] =
+                Cvt<R, V>::out(s);
         }
     }
     if (EPI == EPI_DOT || (EPI == EPI_CHEB && a.dot)) {
@@ -611,11 +622,11 @@ __device__ __forceinline__ void apply_body(const ApplyArgsT<R>& a, R* lds,
     __launch_bounds__(APPLY_THREADS) \
     __attribute__((amdgpu_waves_per_eu(sizeof(R) == 4 ? 3 : RLS_APPLY_WAVES)))
 
-template <int PRO, int EPI, class R>
-__global__ void RLS_APPLY_BOUNDS_T(R) k_apply(ApplyArgsT<R> a) {
+template <int PRO, int EPI, class R, class V>
+__global__ void RLS_APPLY_BOUNDS_T(R) k_apply(ApplyArgsT<R, V> a) {
     extern __shared__ double lds_raw[];
     __shared__ double red[APPLY_THREADS];
-    apply_body<PRO, EPI, R>(a, reinterpret_cast<R*>(lds_raw), red);
+    apply_body<PRO, EPI, R, V>(a, reinterpret_cast<R*>(lds_raw), red);
 }
 
 // dynamic LDS may use what the kernel's static LDS leaves of 160 KiB
@@ -627,17 +638,17 @@ static void allow_lds(const void* fn) {
                               (int)(160 * 1024 - stat));
 }
 
-template <int PRO, int EPI, class R>
-static void launch_one(const ApplyArgsT<R>& a, hipStream_t s) {
+template <int PRO, int EPI, class R, class V>
+static void launch_one(const ApplyArgsT<R, V>& a, hipStream_t s) {
     const TileShape T(a.g, EPI == EPI_RESTRICT);
     dim3 grid((a.g.nv + TILE_Y - 1) / TILE_Y, (a.g.nh + TILE_X - 1) / TILE_X,
               a.nslot);
-    hipLaunchKernelGGL((k_apply<PRO, EPI, R>), grid, dim3(APPLY_THREADS),
+    hipLaunchKernelGGL((k_apply<PRO, EPI, R, V>), grid, dim3(APPLY_THREADS),
                        sizeof(R) * T.lds_elems(), s, a);
 }
 
 // Every (prologue, epilogue) pair in use: all of them in FP64, the V-cycle's
-// (and the plain product) in FP32.
+// (and the plain product) in FP32, with FP32 or BF16 vectors.
 #define RLS_APPLY_VARIANTS_F64(X)     \
     X(PRO_PUPDATE, EPI_DOT)           \
     X(PRO_JACOBI, EPI_CHEB)           \
@@ -661,12 +672,15 @@ static void launch_one(const ApplyArgsT<R>& a, hipStream_t s) {
 void configure_apply_kernels() {
     static bool done = false;
     if (done) return;
-#define RLS_CFG64(P, E) allow_lds((const void*)k_apply<P, E, double>);
-#define RLS_CFG32(P, E) allow_lds((const void*)k_apply<P, E, float>);
+#define RLS_CFG64(P, E) allow_lds((const void*)k_apply<P, E, double, double>);
+#define RLS_CFG32(P, E) allow_lds((const void*)k_apply<P, E, float, float>);
+#define RLS_CFG16(P, E) allow_lds((const void*)k_apply<P, E, float, bf16>);
     RLS_APPLY_VARIANTS_F64(RLS_CFG64)
     RLS_APPLY_VARIANTS_F32(RLS_CFG32)
+    RLS_APPLY_VARIANTS_F32(RLS_CFG16)
 #undef RLS_CFG64
 #undef RLS_CFG32
+#undef RLS_CFG16
     (void)hipGetLastError();
     done = true;
 }
@@ -698,6 +712,10 @@ void launch_smooth_fine(const ApplyArgsT<float>& a, hipStream_t s) {
     if (!launch_smooth_fine_tiled(a, s))
         launch_one<PRO_PLAIN, EPI_CHEB, float>(a, s);
 }
+void launch_smooth_fine(const ApplyArgsT<float, bf16>& a, hipStream_t s) {
+    if (!launch_smooth_fine_tiled(a, s))
+        launch_one<PRO_PLAIN, EPI_CHEB, float, bf16>(a, s);
+}
 
 void launch_apply(int pro, int epi, const ApplyArgsT<double>& a, hipStream_t s) {
 #define RLS_LAUNCH(P, E) \
@@ -716,6 +734,17 @@ void launch_apply(int pro, int epi, const ApplyArgsT<float>& a, hipStream_t s) {
 #undef RLS_LAUNCH
     std::fprintf(stderr, "rls: no FP32 level-operator kernel for prologue %d, "
                          "epilogue %d\n", pro, epi);
+    std::abort();
+}
+
+void launch_apply(int pro, int epi, const ApplyArgsT<float, bf16>& a,
+                  hipStream_t s) {
+#define RLS_LAUNCH(P, E) \
+    if (pro == P && epi == E) { launch_one<P, E, float, bf16>(a, s); return; }
+    RLS_APPLY_VARIANTS_F32(RLS_LAUNCH)
+#undef RLS_LAUNCH
+    std::fprintf(stderr, "rls: no BF16-vector level-operator kernel for "
+                         "prologue %d, epilogue %d\n", pro, epi);
     std::abort();
 }
 

@@ -76,12 +76,12 @@ struct FineShape {
 // scalar-cache lines so that they arrive in one batch (the general argument
 // block spreads them over a kilobyte, and the compiler fetches it line by
 // line between branches).
-template <class R>
+template <class R, class V>
 struct FineArgs {
-    const R* in;            // x of every slot
-    R* out;                 // x + d
-    R* d;                   // Chebyshev direction, in place
-    const R* f;             // right-hand side
+    const V* in;            // x of every slot (storage type V)
+    V* out;                 // x + d
+    V* d;                   // Chebyshev direction, in place
+    const V* f;             // right-hand side
     const R* sn;            // stencil planes: north, east couplings
     const R* se;
     const R* dv;            // diag G_v (nv), diag G_h (nh)
@@ -108,7 +108,8 @@ __device__ __forceinline__ int fine_map(int x, int n, bool wrap) {
     return x < 0 ? lo : (x >= n ? hi : x);
 }
 
-// Four consecutive elements at a 16-byte aligned element index.
+// Four consecutive elements at an element index aligned to four elements
+// (16 bytes for FP32 and FP64, 8 for BF16), converted to R.
 template <class R>
 __device__ __forceinline__ void ld4(const R* base, uint32_t idx, R (&o)[4]) {
     const char* p =
@@ -122,6 +123,16 @@ __device__ __forceinline__ void ld4(const R* base, uint32_t idx, R (&o)[4]) {
         o[0] = a.x; o[1] = a.y; o[2] = a.z; o[3] = a.w;
     }
 }
+template <class R>
+__device__ __forceinline__ void ld4(const bf16* base, uint32_t idx,
+                                    R (&o)[4]) {
+    const uint2 a = *reinterpret_cast<const uint2*>(
+        reinterpret_cast<const char*>(base) + idx * 2u);
+    o[0] = (R)__uint_as_float(a.x << 16);
+    o[1] = (R)__uint_as_float(a.x & 0xffff0000u);
+    o[2] = (R)__uint_as_float(a.y << 16);
+    o[3] = (R)__uint_as_float(a.y & 0xffff0000u);
+}
 
 template <class R>
 __device__ __forceinline__ void st4(R* base, uint32_t idx, const R (&v)[4]) {
@@ -133,11 +144,20 @@ __device__ __forceinline__ void st4(R* base, uint32_t idx, const R (&v)[4]) {
         *reinterpret_cast<float4*>(p) = make_float4(v[0], v[1], v[2], v[3]);
     }
 }
-
 template <class R>
-__device__ __forceinline__ R ldg(const R* base, uint32_t idx) {
-    return *reinterpret_cast<const R*>(reinterpret_cast<const char*>(base) +
-                                       idx * (uint32_t)sizeof(R));
+__device__ __forceinline__ void st4(bf16* base, uint32_t idx,
+                                    const R (&v)[4]) {
+    uint32_t h[4];
+#pragma unroll
+    for (int o = 0; o < 4; ++o) h[o] = float_to_bf16((float)v[o]).bits;
+    *reinterpret_cast<uint2*>(reinterpret_cast<char*>(base) + idx * 2u) =
+        make_uint2(h[0] | (h[1] << 16), h[2] | (h[3] << 16));
+}
+
+template <class R, class V>
+__device__ __forceinline__ R ldg(const V* base, uint32_t idx) {
+    return Cvt<R, V>::in(*reinterpret_cast<const V*>(
+        reinterpret_cast<const char*>(base) + idx * (uint32_t)sizeof(V)));
 }
 
 // n consecutive LDS elements from a 16-byte aligned address.
@@ -181,11 +201,11 @@ __device__ __forceinline__ float shfl_up16(float v) {
     return __shfl_up(v, 16, 64);
 }
 
-template <class R, int BW>
+template <class R, class V, int BW>
 __global__ void __launch_bounds__(FT)
-k_smooth_fine(FineArgs<R> a) {
+k_smooth_fine(FineArgs<R, V> a) {
     using S = FineShape<R, BW>;
-    using V = typename Vec16<R>::T;
+    using VT = typename Vec16<R>::T;   // 16 bytes of R
     extern __shared__ __align__(16) double lds_raw[];
     __shared__ double red[FT];
     R* vin = reinterpret_cast<R*>(lds_raw);      // RY x SX, row-major
@@ -221,10 +241,10 @@ k_smooth_fine(FineArgs<R> a) {
     const int tx = tile % ntx, ty = tile / ntx;
     const int i0 = tx * FY, j0 = ty * FX;
     const size_t so = (size_t)slot * ((size_t)nv * nh);
-    const R* src = a.in + so;
-    const R* f = a.f_shared ? a.f : a.f + so;
-    R* dir = a.d + so;
-    R* out = a.out + so;
+    const V* src = a.in + so;
+    const V* f = a.f_shared ? a.f : a.f + so;
+    V* dir = a.d + so;
+    V* out = a.out + so;
     const bool wrapv = a.wrapv, wraph = a.wraph;
     const int per = a.per;
 
@@ -244,7 +264,7 @@ k_smooth_fine(FineArgs<R> a) {
     const int lane = t & 63;
     R pf[4], pd[4], psn[4], pse[4], psw[4], dgr[4];
     ld4(f, p0, pf);
-    ld4((const R*)dir, p0, pd);
+    ld4((const V*)dir, p0, pd);
     ld4(a.sn, p0, psn);
     ld4(a.se, p0, pse);
     const R dgh = a.dh[gj];
@@ -252,8 +272,8 @@ k_smooth_fine(FineArgs<R> a) {
 #pragma unroll
     for (int o = 0; o < 4; ++o) psw[o] = dgr[o] = R(0);
     if (lane < 16) {
-        if (gi0 > 0) pss0 = ldg(a.sn, p0 - 1);
-        else if (per) pss0 = ldg(a.sn, (uint32_t)(nv - 1) + (uint32_t)nv * gj);
+        if (gi0 > 0) pss0 = ldg<R>(a.sn, p0 - 1);
+        else if (per) pss0 = ldg<R>(a.sn, (uint32_t)(nv - 1) + (uint32_t)nv * gj);
     }
     if (c == 0) {
         if (gj > 0) ld4(a.se, p0 - (uint32_t)nv, psw);
@@ -272,14 +292,14 @@ k_smooth_fine(FineArgs<R> a) {
     int ii = t % S::RY, jq = t / S::RY;
     constexpr int DI = FT % S::RY, DJ = FT / S::RY;
     if (inner) {
-        const R* sb = src + (size_t)(i0 - BW) + (size_t)nv * (size_t)(j0 - BW);
+        const V* sb = src + (size_t)(i0 - BW) + (size_t)nv * (size_t)(j0 - BW);
 #pragma unroll
         for (int k = 0; k < S::UPT; ++k) {
             const uint32_t o = (uint32_t)ii + (uint32_t)nv * (uint32_t)(jq * S::VEC);
 #pragma unroll
             for (int cc = 0; cc < S::VEC; ++cc)
                 u[k][cc] = t + FT * k < S::NU
-                               ? ldg(sb, o + (uint32_t)nv * (uint32_t)cc)
+                               ? ldg<R>(sb, o + (uint32_t)nv * (uint32_t)cc)
                                : R(0);
             ii += DI;
             jq += DJ;
@@ -295,7 +315,7 @@ k_smooth_fine(FineArgs<R> a) {
                 if (t + FT * k < S::NU) {
                     const int gjj =
                         fine_map(j0 - BW + jq * S::VEC + cc, nh, wraph);
-                    u[k][cc] = ldg(src, gi + (uint32_t)nv * (uint32_t)gjj);
+                    u[k][cc] = ldg<R>(src, gi + (uint32_t)nv * (uint32_t)gjj);
                 }
             }
             ii += DI;
@@ -317,13 +337,13 @@ k_smooth_fine(FineArgs<R> a) {
         const int e = t + FT * k;
         if (e < S::NU) {
             const int ii = e % S::RY, jq = e / S::RY;
-            V x;
+            VT x;
             if constexpr (S::VEC == 2) {
                 x.x = u[k][0]; x.y = u[k][1];
             } else {
                 x.x = u[k][0]; x.y = u[k][1]; x.z = u[k][2]; x.w = u[k][3];
             }
-            *reinterpret_cast<V*>(vin + ii * S::SX + jq * S::VEC) = x;
+            *reinterpret_cast<VT*>(vin + ii * S::SX + jq * S::VEC) = x;
         }
     }
     __syncthreads();
@@ -407,8 +427,8 @@ bool aligned16(const void* p) {
     return ((uintptr_t)p & 15) == 0;
 }
 
-template <class R>
-int fine_radius(const ApplyArgsT<R>& a) {
+template <class R, class V>
+int fine_radius(const ApplyArgsT<R, V>& a) {
     const LevelGeomT<R>& g = a.g;
     if (g.ct.on || !g.gv.uniform || !g.gh.uniform || g.S.nine) return -1;
     if (g.gv.map == MAP_ZERO || g.gh.map == MAP_ZERO) return -1;
@@ -426,10 +446,10 @@ int fine_radius(const ApplyArgsT<R>& a) {
     return bw <= FBW ? bw : -1;
 }
 
-template <class R>
-FineArgs<R> fine_args(const ApplyArgsT<R>& a, int bw) {
+template <class R, class V>
+FineArgs<R, V> fine_args(const ApplyArgsT<R, V>& a, int bw) {
     const LevelGeomT<R>& g = a.g;
-    FineArgs<R> f{};
+    FineArgs<R, V> f{};
     f.in = a.in;
     f.out = a.out;
     f.d = a.d;
@@ -461,25 +481,25 @@ FineArgs<R> fine_args(const ApplyArgsT<R>& a, int bw) {
     return f;
 }
 
-template <class R, int BW>
-void launch_fine(const ApplyArgsT<R>& a, hipStream_t s) {
+template <class R, class V, int BW>
+void launch_fine(const ApplyArgsT<R, V>& a, hipStream_t s) {
     using Sh = FineShape<R, BW>;
     dim3 grid(a.g.nv / FY, a.g.nh / FX, a.nslot);
-    hipLaunchKernelGGL((k_smooth_fine<R, BW>), grid, dim3(FT), Sh::lds_bytes, s,
-                       fine_args(a, BW));
+    hipLaunchKernelGGL((k_smooth_fine<R, V, BW>), grid, dim3(FT), Sh::lds_bytes,
+                       s, fine_args(a, BW));
 }
 
-template <class R>
-bool fine_impl(const ApplyArgsT<R>& a, hipStream_t s) {
+template <class R, class V>
+bool fine_impl(const ApplyArgsT<R, V>& a, hipStream_t s) {
     switch (fine_radius(a)) {
-        case 2: launch_fine<R, 2>(a, s); return true;
-        case 4: launch_fine<R, 4>(a, s); return true;
-        case 6: launch_fine<R, 6>(a, s); return true;
-        case 8: launch_fine<R, 8>(a, s); return true;
-        case 10: launch_fine<R, 10>(a, s); return true;
-        case 12: launch_fine<R, 12>(a, s); return true;
-        case 14: launch_fine<R, 14>(a, s); return true;
-        case 16: launch_fine<R, 16>(a, s); return true;
+        case 2: launch_fine<R, V, 2>(a, s); return true;
+        case 4: launch_fine<R, V, 4>(a, s); return true;
+        case 6: launch_fine<R, V, 6>(a, s); return true;
+        case 8: launch_fine<R, V, 8>(a, s); return true;
+        case 10: launch_fine<R, V, 10>(a, s); return true;
+        case 12: launch_fine<R, V, 12>(a, s); return true;
+        case 14: launch_fine<R, V, 14>(a, s); return true;
+        case 16: launch_fine<R, V, 16>(a, s); return true;
         default: return false;
     }
 }
@@ -490,6 +510,9 @@ bool launch_smooth_fine_tiled(const ApplyArgsT<double>& a, hipStream_t s) {
     return fine_impl(a, s);
 }
 bool launch_smooth_fine_tiled(const ApplyArgsT<float>& a, hipStream_t s) {
+    return fine_impl(a, s);
+}
+bool launch_smooth_fine_tiled(const ApplyArgsT<float, bf16>& a, hipStream_t s) {
     return fine_impl(a, s);
 }
 

@@ -199,7 +199,7 @@ k_reduce_slots(const double* __restrict__ part, int nparts,
     if (threadIdx.x == 0) out[slot] = s;
 }
 
-// ---- boundary of the FP32 V-cycle under flexible FP64 PCG ---------------
+// ---- boundary of a reduced-precision V-cycle under flexible FP64 PCG -----
 
 // Narrowing copy dst = (float) src over nslot slots (slot list optional).
 __global__ void __launch_bounds__(VB)
@@ -216,30 +216,33 @@ k_to_f32(const double* __restrict__ src, int64_t n, const int* slots,
 }
 
 // Convergence test on ||r|| (as the FP64 path does in its first V-cycle
-// kernel), then r32 = (float) r for the V-cycle.
+// kernel; skipped when st is null), then rlo = r rounded to the V-cycle's
+// storage type V (float or bf16).
+template <class V>
 __global__ void __launch_bounds__(VB)
 k_vc_enter(SlotState* st, int* active, const int* slots, const double* part_rr,
            int nrr, int64_t n, const double* __restrict__ r,
-           float* __restrict__ r32) {
+           V* __restrict__ rlo) {
     __shared__ double sh[VB];
     const int slot = slots ? slots[blockIdx.y] : (int)blockIdx.y;
-    if (!active[slot]) return;
-    if (!pcg_gate<VB>(st, active, slot, part_rr, nrr, blockIdx.x == 0, sh))
+    if (active && !active[slot]) return;
+    if (st && !pcg_gate<VB>(st, active, slot, part_rr, nrr, blockIdx.x == 0, sh))
         return;
     const size_t base = (size_t)slot * n;
     const int64_t p0 = (int64_t)blockIdx.x * VCHUNK + threadIdx.x;
 #pragma unroll
     for (int k = 0; k < VPT; ++k) {
         const int64_t p = p0 + (int64_t)k * VB;
-        if (p < n) r32[base + p] = (float)r[base + p];
+        if (p < n) rlo[base + p] = Cvt<double, V>::out(r[base + p]);
     }
 }
 
-// z = (double) z32 and the partials of r . z and z . q ([slot][part], npart
-// parts of n / npart consecutive points each).
+// z = zlo widened to FP64 and the partials of r . z and z . q ([slot][part],
+// npart parts of n / npart consecutive points each).
+template <class V>
 __global__ void __launch_bounds__(VB)
 k_vc_exit(const int* slots, const int* active, int64_t n, int npart,
-          const float* __restrict__ z32, double* __restrict__ z,
+          const V* __restrict__ zlo, double* __restrict__ z,
           const double* __restrict__ r, const double* __restrict__ q,
           double* part_rz, double* part_zq) {
     __shared__ double sh[VB];
@@ -251,7 +254,7 @@ k_vc_exit(const int* slots, const int* active, int64_t n, int npart,
     const int64_t hi = lo + len < n ? lo + len : n;
     double rz = 0.0, zq = 0.0;
     for (int64_t p = lo + threadIdx.x; p < hi; p += VB) {
-        const double zv = (double)z32[base + p];
+        const double zv = Cvt<double, V>::in(zlo[base + p]);
         z[base + p] = zv;
         rz += r[base + p] * zv;
         if (q) zq += zv * q[base + p];
@@ -325,19 +328,32 @@ void launch_to_f32(const double* src, int64_t n, int nslot, const int* slots,
                        src, n, slots, dst);
 }
 
+template <class V>
 void launch_vc_enter(SlotState* st, int* active, const int* slots, int nslot,
                      const double* part_rr, int nrr, int64_t n, const double* r,
-                     float* r32, hipStream_t s) {
-    hipLaunchKernelGGL(k_vc_enter, dim3(vec_blocks(n), nslot), dim3(VB), 0, s,
-                       st, active, slots, part_rr, nrr, n, r, r32);
+                     V* rlo, hipStream_t s) {
+    hipLaunchKernelGGL(k_vc_enter<V>, dim3(vec_blocks(n), nslot), dim3(VB), 0,
+                       s, st, active, slots, part_rr, nrr, n, r, rlo);
 }
 
+template <class V>
 void launch_vc_exit(const int* slots, const int* active, int nslot, int64_t n,
-                    int npart, const float* z32, double* z, const double* r,
+                    int npart, const V* zlo, double* z, const double* r,
                     const double* q, double* part_rz, double* part_zq,
                     hipStream_t s) {
-    hipLaunchKernelGGL(k_vc_exit, dim3(npart, nslot), dim3(VB), 0, s, slots,
-                       active, n, npart, z32, z, r, q, part_rz, part_zq);
+    hipLaunchKernelGGL(k_vc_exit<V>, dim3(npart, nslot), dim3(VB), 0, s, slots,
+                       active, n, npart, zlo, z, r, q, part_rz, part_zq);
 }
+
+template void launch_vc_enter(SlotState*, int*, const int*, int, const double*,
+                              int, int64_t, const double*, float*, hipStream_t);
+template void launch_vc_enter(SlotState*, int*, const int*, int, const double*,
+                              int, int64_t, const double*, bf16*, hipStream_t);
+template void launch_vc_exit(const int*, const int*, int, int64_t, int,
+                             const float*, double*, const double*,
+                             const double*, double*, double*, hipStream_t);
+template void launch_vc_exit(const int*, const int*, int, int64_t, int,
+                             const bf16*, double*, const double*,
+                             const double*, double*, double*, hipStream_t);
 
 }  // namespace rls

@@ -157,7 +157,7 @@ __global__ void __launch_bounds__(TAIL_THREADS) k_tail(TailArgsT<IO> a) {
     sc.res = q + 3 * nt;
 
     for (int p = threadIdx.x; p < n0; p += TAIL_THREADS)
-        F[0][p] = (double)a.f[(size_t)slot * n0 + p];
+        F[0][p] = Cvt<double, IO>::in(a.f[(size_t)slot * n0 + p]);
     __syncthreads();
 
     // down: smooth, residual, restrict
@@ -256,7 +256,7 @@ __global__ void __launch_bounds__(TAIL_THREADS) k_tail(TailArgsT<IO> a) {
     double dot = 0.0;
     for (int p = threadIdx.x; p < n0; p += TAIL_THREADS) {
         const double zv = X[0][p];
-        a.z[(size_t)slot * n0 + p] = (IO)zv;
+        a.z[(size_t)slot * n0 + p] = Cvt<double, IO>::out(zv);
         dot += F[0][p] * zv;
     }
     if (a.dot) {
@@ -276,6 +276,7 @@ size_t tail_lds_bytes(const TailArgsT<IO>& a) {
 }
 template size_t tail_lds_bytes(const TailArgsT<double>&);
 template size_t tail_lds_bytes(const TailArgsT<float>&);
+template size_t tail_lds_bytes(const TailArgsT<bf16>&);
 
 template <class IO>
 static void tail_impl(const TailArgsT<IO>& a, int nslot, hipStream_t s) {
@@ -299,6 +300,9 @@ void launch_tail(const TailArgsT<double>& a, int nslot, hipStream_t s) {
     tail_impl(a, nslot, s);
 }
 void launch_tail(const TailArgsT<float>& a, int nslot, hipStream_t s) {
+    tail_impl(a, nslot, s);
+}
+void launch_tail(const TailArgsT<bf16>& a, int nslot, hipStream_t s) {
     tail_impl(a, nslot, s);
 }
 

@@ -14,6 +14,43 @@ namespace rls {
 // Index extension of a 1D direction when reading outside [0, n).
 enum MapKind : int { MAP_ZERO = 0, MAP_WRAP = 1, MAP_REFLECT = 2 };
 
+// BF16 storage element: the upper half of an IEEE FP32 value.  Stores round
+// to nearest, ties to even; finite values beyond the BF16 range become
+// infinities, as IEEE rounding prescribes.
+struct bf16 {
+    uint16_t bits;
+};
+__host__ __device__ inline float bf16_to_float(bf16 x) {
+    return __builtin_bit_cast(float, (uint32_t)x.bits << 16);
+}
+__host__ __device__ inline bf16 float_to_bf16(float f) {
+    uint32_t u = __builtin_bit_cast(uint32_t, f);
+    u += 0x7fffu + ((u >> 16) & 1u);
+    return bf16{(uint16_t)(u >> 16)};
+}
+
+// Conversions between a storage type V and an arithmetic type R.
+template <class R, class V>
+struct Cvt {
+    __host__ __device__ static R in(V v) { return (R)v; }
+    __host__ __device__ static V out(R r) { return (V)r; }
+};
+template <class R>
+struct Cvt<R, bf16> {
+    __host__ __device__ static R in(bf16 v) { return (R)bf16_to_float(v); }
+    __host__ __device__ static bf16 out(R r) { return float_to_bf16((float)r); }
+};
+
+// Arithmetic type of the V-cycle for a vector storage type.
+template <class V>
+struct CompOf {
+    using T = V;
+};
+template <>
+struct CompOf<bf16> {
+    using T = float;
+};
+
 // A banded n x n operator along one image axis.  Row r, offset k in
 // [-bw, bw] is the coefficient of x(map(r + k)).  `uniform` rows all equal
 // `taps` (the index map supplies the boundary); otherwise `table` holds
@@ -123,11 +160,11 @@ struct SlotState {
 // through the scalar kernel-argument path instead of a global load).
 constexpr int ZINLINE = 32;
 
-// Arguments of the level-operator kernel; R is the value type of the
-// level's vectors, bands and stencil (double, or float for the FP32
-// V-cycle).  Per-slot scalars, Chebyshev coefficients and partial sums are
-// always double.
-template <class R>
+// Arguments of the level-operator kernel; R is the arithmetic type and the
+// type of the level's bands and stencil (double, or float for the FP32 and
+// BF16 V-cycles), V the storage type of its vectors (R, or bf16).  Per-slot
+// scalars, Chebyshev coefficients and partial sums are always double.
+template <class R, class V = R>
 struct ApplyArgsT {
     LevelGeomT<R> g;
     int nslot = 0;                   // grid z: number of slots launched
@@ -136,19 +173,19 @@ struct ApplyArgsT {
     int zslot[ZINLINE] = {};
     const double* lam2 = nullptr;    // per slot lambda^2
     const int* active = nullptr;     // per slot, may be null (all active)
-    const R* in = nullptr;           // v, z (PUPDATE) or x (PROLONG)
-    const R* pold = nullptr;         // PRO_PUPDATE
-    R* pnew = nullptr;               // PRO_PUPDATE
+    const V* in = nullptr;           // v, z (PUPDATE) or x (PROLONG)
+    const V* pold = nullptr;         // PRO_PUPDATE
+    V* pnew = nullptr;               // PRO_PUPDATE
     const double* beta = nullptr;    // PRO_PUPDATE, per slot
-    const R* ec = nullptr;           // PRO_PROLONG coarse correction
-    R* out = nullptr;
-    const R* f = nullptr;            // right-hand side (RESID/CHEB/RESTRICT/JACOBI)
+    const V* ec = nullptr;           // PRO_PROLONG coarse correction
+    V* out = nullptr;
+    const V* f = nullptr;            // right-hand side (RESID/CHEB/RESTRICT/JACOBI)
     int f_shared = 0;                // f has one vector for all slots
-    R* d = nullptr;                  // EPI_CHEB direction, in place
+    V* d = nullptr;                  // EPI_CHEB direction, in place
     const double* cheb = nullptr;    // per slot (c1, c2) of this step
     const double* cheb_first = nullptr;  // PRO_JACOBI: (c1, c2) of step 0
     int cheb_stride = 0;             // doubles between slots in cheb
-    R* fc = nullptr;                 // EPI_RESTRICT coarse right-hand side
+    V* fc = nullptr;                 // EPI_RESTRICT coarse right-hand side
     int dot = 0;                     // EPI_CHEB: accumulate f . out
     double* part = nullptr;          // partial sums [slot][tile]
     int part_stride = 0;             // tiles per slot in part
@@ -168,6 +205,8 @@ using ApplyArgs = ApplyArgsT<double>;
 
 void launch_apply(int pro, int epi, const ApplyArgsT<double>& a, hipStream_t s);
 void launch_apply(int pro, int epi, const ApplyArgsT<float>& a, hipStream_t s);
+void launch_apply(int pro, int epi, const ApplyArgsT<float, bf16>& a,
+                  hipStream_t s);
 void configure_apply_kernels();  // LDS limits of every variant, once
 // Finest-level Chebyshev step (plain prologue, launch_apply(PRO_PLAIN,
 // EPI_CHEB) arithmetic): the tiled kernel of k_fine.hip when the level
@@ -176,9 +215,11 @@ void configure_apply_kernels();  // LDS limits of every variant, once
 // kernel.
 void launch_smooth_fine(const ApplyArgsT<double>& a, hipStream_t s);
 void launch_smooth_fine(const ApplyArgsT<float>& a, hipStream_t s);
+void launch_smooth_fine(const ApplyArgsT<float, bf16>& a, hipStream_t s);
 // false when the level does not qualify (nothing launched)
 bool launch_smooth_fine_tiled(const ApplyArgsT<double>& a, hipStream_t s);
 bool launch_smooth_fine_tiled(const ApplyArgsT<float>& a, hipStream_t s);
+bool launch_smooth_fine_tiled(const ApplyArgsT<float, bf16>& a, hipStream_t s);
 
 // ---- setup kernels (k_setup.hip) ------------------------------------
 void launch_blur_band(const double* taps, int r, int n, int bc, double* band,
@@ -272,11 +313,16 @@ void launch_coarse_assemble_ct(const LevelGeom& g, const double* G,
 // FP32 V-cycle boundary (k_pcg.hip)
 void launch_to_f32(const double* src, int64_t n, int nslot, const int* slots,
                    float* dst, hipStream_t s);
+// Boundary of a reduced-precision V-cycle (V = float or bf16): narrowing of
+// r (after the convergence test when st is given), widening of z with the
+// partials of r . z (and z . q).
+template <class V>
 void launch_vc_enter(SlotState* st, int* active, const int* slots, int nslot,
                      const double* part_rr, int nrr, int64_t n, const double* r,
-                     float* r32, hipStream_t s);
+                     V* rlo, hipStream_t s);
+template <class V>
 void launch_vc_exit(const int* slots, const int* active, int nslot, int64_t n,
-                    int npart, const float* z32, double* z, const double* r,
+                    int npart, const V* zlo, double* z, const double* r,
                     const double* q, double* part_rz, double* part_zq,
                     hipStream_t s);
 
@@ -321,6 +367,7 @@ using TailArgs = TailArgsT<double>;
 
 void launch_tail(const TailArgsT<double>& a, int nslot, hipStream_t s);
 void launch_tail(const TailArgsT<float>& a, int nslot, hipStream_t s);
+void launch_tail(const TailArgsT<bf16>& a, int nslot, hipStream_t s);
 template <class IO>
 size_t tail_lds_bytes(const TailArgsT<IO>& a);
 size_t apply_lds_bytes(const LevelGeom& g, int epi);

@@ -117,3 +117,24 @@ def test_batch_argument_checks_without_gpu():
     arr[1].prob = fake
     assert lib.rls_solve_batch(arr, 2, None) == L.RLS_E_ARG
     assert b"twice" in lib.rls_last_error()
+
+
+def test_sparse_operator_rejects_bf16_vcycle_without_gpu():
+    """Sparse (tomography) operators run their V-cycle in FP32 only; the
+    precision is checked on the host before anything reaches the GPU."""
+    lib = L.load()
+    rowptr = (C.c_int64 * 3)(0, 1, 2)
+    col = (C.c_int32 * 2)(0, 1)
+    val = (C.c_float * 2)(1.0, 1.0)
+    op = L.OpDesc()
+    op.kind = L.RLS_OP_CSR
+    op.m, op.nnz = 2, 2
+    op.rowptr = C.cast(rowptr, C.POINTER(C.c_int64))
+    op.col = C.cast(col, C.POINTER(C.c_int32))
+    op.val = C.cast(val, C.POINTER(C.c_float))
+    g = L.GridDesc(64, 64, L.RLS_L_NEUMANN, 3, 2, 4.0, L.RLS_PREC_MIXED_BF16,
+                   0, 0.0)
+    h = C.c_void_p()
+    st = lib.rls_setup(C.byref(h), C.byref(op), C.byref(g), None, None)
+    assert st == L.RLS_E_UNSUPPORTED
+    assert b"FP32" in lib.rls_last_error()
