@@ -276,8 +276,9 @@ rls_status rls_gershgorin(rls_problem* p, int level, const double* lam,
  * rls_kernel_timer_read returns the number of timed launches, their summed
  * duration in seconds and their summed algorithmic bytes: per pixel, 40
  * bytes per active lambda (read x, f, d; write x, d) plus, for launches with
- * an active lambda, 24 bytes of shared stencil coefficients, every array
- * counted once. */
+ * an active lambda, 16 bytes of shared stencil couplings (north and east;
+ * the centre is minus the sum of the four couplings), every array counted
+ * once. */
 rls_status rls_kernel_timer(rls_problem* p, int enable);
 rls_status rls_kernel_timer_read(const rls_problem* p, long long* launches,
                                  double* seconds, double* bytes);

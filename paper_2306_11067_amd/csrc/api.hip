@@ -1624,8 +1624,9 @@ rls_status rls_solve_sweep(rls_problem* p, const double* b, const double* lam,
         drain_timer(p);
         // Every V-cycle of a slot takes part in 2 nu - 3 finest-level
         // Chebyshev-step launches (40 bytes per pixel per slot); a launch
-        // with at least one active slot also reads the three shared stencil
-        // planes (24 bytes per pixel).
+        // with at least one active slot also reads the two shared stencil
+        // coupling planes (16 bytes per pixel; the centre coefficient is
+        // minus their sum on the finest level).
         const int nu0 = p->nu[0];
         const int per_cycle =
             (p->kt > 0 && nu0 >= 2 && p->prec == RLS_PREC_FP64) ? 2 * nu0 - 3 : 0;
@@ -1636,7 +1637,7 @@ rls_status rls_solve_sweep(rls_problem* p, const double* b, const double* lam,
             max_cycles = std::max(max_cycles, hst[i].ncycle);
         }
         p->timer_bytes += (double)n * 40.0 * slot_launches +
-                          (double)n * 24.0 * (double)max_cycles * per_cycle;
+                          (double)n * 16.0 * (double)max_cycles * per_cycle;
     }
     for (int i = 0; i < ns; ++i) {
         if (resnorm) resnorm[i] = std::sqrt(h3[ns + i]);

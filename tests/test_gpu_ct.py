@@ -47,6 +47,25 @@ def test_ct_forward_adjoint_match_scipy(case):
                                    atol=1e-12 * np.abs(want).max())
 
 
+def test_ct_grouped_products_equal_single_products(case):
+    """Products over several vectors take the kernel that reads each row of
+    A once for a group of vectors; it sums in the same order as the
+    one-vector kernel, so every vector's result is bitwise the same as
+    computing it alone (and equals SciPy's within rounding)."""
+    P, prob, O = case
+    rng = np.random.default_rng(2)
+    k = 9                                   # one group of 8, one of 1
+    x = rng.standard_normal(k * P.n)
+    y = rng.standard_normal(k * P.m)
+    ax = host(prob.forward(dev(x), nvec=k))
+    aty = host(prob.adjoint(dev(y), nvec=k))
+    for s in range(k):
+        one = host(prob.forward(dev(x[s * P.n:(s + 1) * P.n]), nvec=1))
+        assert np.array_equal(ax[s * P.m:(s + 1) * P.m], one), s
+        one = host(prob.adjoint(dev(y[s * P.m:(s + 1) * P.m]), nvec=1))
+        assert np.array_equal(aty[s * P.n:(s + 1) * P.n], one), s
+
+
 def test_ct_level_operators_match_oracle(case):
     P, prob, O = case
     H = O.H
