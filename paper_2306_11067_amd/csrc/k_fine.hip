@@ -30,10 +30,13 @@ namespace {
 
 constexpr int FY = 64;    // output rows per tile (contiguous axis)
 constexpr int FX = 16;    // output columns per tile
-constexpr int FT = 256;   // threads
-constexpr int HWO = 8;    // horizontal-pass outputs per thread
-constexpr int VWO = 4;    // vertical-pass outputs per thread
 constexpr int FZ = 64;    // most slots per launch (the slot list is inline)
+// Launches with at most this many slots use 512-thread workgroups: with one
+// workgroup per CU the passes then run on two waves per SIMD.  Measured at
+// 512 x 512, one PCG iteration with graph replay: one slot 2.54 ms against
+// 2.62 (FP64) and 2.36 against 2.39 (FP32 V-cycle); two slots 3.34 against
+// 3.39 (FP64) but 2.88 against 2.68 (FP32).
+constexpr int FWIDE_MAX = 1;
 constexpr int FBW = 16;   // largest band radius with a specialised kernel
 
 template <class R>
@@ -47,8 +50,12 @@ struct Vec16<float> {
     using T = float4;
 };
 
-template <class R, int BW>
+// Tile geometry for band radius BW and NT threads (256: 8 horizontal
+// outputs and 4 vertical outputs per thread; 512: 4 and 2).
+template <class R, int BW, int NT>
 struct FineShape {
+    static constexpr int HWO = NT == 256 ? 8 : 4;      // horizontal outputs
+    static constexpr int VWO = NT == 256 ? 4 : 2;      // vertical outputs
     static constexpr int VEC = 16 / (int)sizeof(R);   // elements per 16 bytes
     static constexpr int RY = FY + 2 * BW;            // input rows
     static constexpr int CX = FX + 2 * BW;            // input columns
@@ -59,17 +66,21 @@ struct FineShape {
     static constexpr int SX = (((CX + VEC - 1) / VEC) | 1) * VEC;
     static constexpr int SH = (((RY + VEC - 1) / VEC) | 1) * VEC;
     static constexpr int NU = RY * (CX / VEC);        // load units
-    static constexpr int UPT = (NU + FT - 1) / FT;    // units per thread
+    static constexpr int UPT = (NU + NT - 1) / NT;    // units per thread
     static constexpr int HWL = HWO + 2 * BW;          // horizontal window
     static constexpr int VWL = VWO + 2 * BW;          // vertical window
+    // vertical windows start at multiples of VWO rows: 16-byte reads when
+    // that is a multiple of VEC, else 8-byte reads
+    static constexpr int VCW = VWO % VEC == 0 ? VEC : 8 / (int)sizeof(R);
+    static constexpr int NH = (FX / HWO) * RY;        // horizontal items
     // input tile, horizontal-pass result, diag G_v of the tile's rows
     static constexpr size_t lds_bytes =
         sizeof(R) * ((size_t)RY * SX + (size_t)FX * SH + FY);
     static_assert(BW % 2 == 0, "even band radius");
     static_assert(CX % VEC == 0, "whole load units per row");
-    static_assert(HWL % VEC == 0 && VWL % VEC == 0, "whole vector windows");
-    static_assert(2 * RY <= FT, "one horizontal item per thread");
-    static_assert((FY / VWO) * FX == FT, "one vertical item per thread");
+    static_assert(HWL % VEC == 0 && VWL % VCW == 0, "whole vector windows");
+    static_assert(NH <= NT, "one horizontal item per thread");
+    static_assert((FY / VWO) * FX == NT, "one vertical item per thread");
 };
 
 // Everything one launch reads from its kernel arguments, packed into a few
@@ -154,26 +165,83 @@ __device__ __forceinline__ void st4(bf16* base, uint32_t idx,
         make_uint2(h[0] | (h[1] << 16), h[2] | (h[3] << 16));
 }
 
+// Two consecutive elements at an even element index, converted to R.
+template <class R>
+__device__ __forceinline__ void ld2(const R* base, uint32_t idx, R (&o)[2]) {
+    const char* p =
+        reinterpret_cast<const char*>(base) + idx * (uint32_t)sizeof(R);
+    if constexpr (sizeof(R) == 8) {
+        const double2 a = *reinterpret_cast<const double2*>(p);
+        o[0] = a.x; o[1] = a.y;
+    } else {
+        const float2 a = *reinterpret_cast<const float2*>(p);
+        o[0] = a.x; o[1] = a.y;
+    }
+}
+template <class R>
+__device__ __forceinline__ void ld2(const bf16* base, uint32_t idx,
+                                    R (&o)[2]) {
+    const uint32_t a = *reinterpret_cast<const uint32_t*>(
+        reinterpret_cast<const char*>(base) + idx * 2u);
+    o[0] = (R)__uint_as_float(a << 16);
+    o[1] = (R)__uint_as_float(a & 0xffff0000u);
+}
+template <class R>
+__device__ __forceinline__ void st2(R* base, uint32_t idx, const R (&v)[2]) {
+    char* p = reinterpret_cast<char*>(base) + idx * (uint32_t)sizeof(R);
+    if constexpr (sizeof(R) == 8)
+        *reinterpret_cast<double2*>(p) = make_double2(v[0], v[1]);
+    else
+        *reinterpret_cast<float2*>(p) = make_float2(v[0], v[1]);
+}
+template <class R>
+__device__ __forceinline__ void st2(bf16* base, uint32_t idx,
+                                    const R (&v)[2]) {
+    *reinterpret_cast<uint32_t*>(reinterpret_cast<char*>(base) + idx * 2u) =
+        (uint32_t)float_to_bf16((float)v[0]).bits |
+        ((uint32_t)float_to_bf16((float)v[1]).bits << 16);
+}
+// N = 2 or 4 consecutive elements
+template <class R, class T, int N>
+__device__ __forceinline__ void ldn(const T* base, uint32_t idx, R (&o)[N]) {
+    if constexpr (N == 4) ld4(base, idx, o);
+    else ld2(base, idx, o);
+}
+template <class R, class T, int N>
+__device__ __forceinline__ void stn(T* base, uint32_t idx, const R (&v)[N]) {
+    if constexpr (N == 4) st4(base, idx, v);
+    else st2(base, idx, v);
+}
+
 template <class R, class V>
 __device__ __forceinline__ R ldg(const V* base, uint32_t idx) {
     return Cvt<R, V>::in(*reinterpret_cast<const V*>(
         reinterpret_cast<const char*>(base) + idx * (uint32_t)sizeof(V)));
 }
 
-// n consecutive LDS elements from a 16-byte aligned address.
-template <class R, int N>
+// N consecutive LDS elements read CW at a time (CW * sizeof(R) = 16 or 8
+// bytes, the address aligned to that).
+template <class R, int N, int CW = 16 / (int)sizeof(R)>
 __device__ __forceinline__ void lds_window(const R* p, R (&w)[N]) {
-    using V = typename Vec16<R>::T;
-    constexpr int VEC = 16 / (int)sizeof(R);
-    static_assert(N % VEC == 0, "whole vectors");
+    static_assert(N % CW == 0, "whole chunks");
+    if constexpr (CW * sizeof(R) == 16) {
+        using V = typename Vec16<R>::T;
 #pragma unroll
-    for (int m = 0; m < N / VEC; ++m) {
-        const V x = reinterpret_cast<const V*>(p)[m];
-        if constexpr (VEC == 2) {
+        for (int m = 0; m < N / CW; ++m) {
+            const V x = reinterpret_cast<const V*>(p)[m];
+            if constexpr (CW == 2) {
+                w[2 * m] = x.x; w[2 * m + 1] = x.y;
+            } else {
+                w[4 * m] = x.x; w[4 * m + 1] = x.y;
+                w[4 * m + 2] = x.z; w[4 * m + 3] = x.w;
+            }
+        }
+    } else {   // 8-byte chunks of two floats
+        static_assert(CW == 2 && sizeof(R) == 4, "8-byte chunks of FP32");
+#pragma unroll
+        for (int m = 0; m < N / 2; ++m) {
+            const float2 x = reinterpret_cast<const float2*>(p)[m];
             w[2 * m] = x.x; w[2 * m + 1] = x.y;
-        } else {
-            w[4 * m] = x.x; w[4 * m + 1] = x.y;
-            w[4 * m + 2] = x.z; w[4 * m + 3] = x.w;
         }
     }
 }
@@ -201,13 +269,14 @@ __device__ __forceinline__ float shfl_up16(float v) {
     return __shfl_up(v, 16, 64);
 }
 
-template <class R, class V, int BW>
-__global__ void __launch_bounds__(FT)
+template <class R, class V, int BW, int NT>
+__global__ void __launch_bounds__(NT)
 k_smooth_fine(FineArgs<R, V> a) {
-    using S = FineShape<R, BW>;
+    using S = FineShape<R, BW, NT>;
+    constexpr int HWO = S::HWO, VWO = S::VWO;
     using VT = typename Vec16<R>::T;   // 16 bytes of R
     extern __shared__ __align__(16) double lds_raw[];
-    __shared__ double red[FT];
+    __shared__ double red[NT];
     R* vin = reinterpret_cast<R*>(lds_raw);      // RY x SX, row-major
     R* ht = vin + S::RY * S::SX;                 // FX x SH, column-major
     R* dgl = ht + FX * S::SH;                    // FY: diag G_v, rows i0..
@@ -262,35 +331,37 @@ k_smooth_fine(FineArgs<R, V> a) {
     // on a periodic grid, zero across a non-periodic edge).  diag G_v of the
     // tile's 64 rows is loaded once per tile into LDS.
     const int lane = t & 63;
-    R pf[4], pd[4], psn[4], pse[4], psw[4], dgr[4];
-    ld4(f, p0, pf);
-    ld4((const V*)dir, p0, pd);
-    ld4(a.sn, p0, psn);
-    ld4(a.se, p0, pse);
+    R pf[VWO], pd[VWO], psn[VWO], pse[VWO], psw[VWO], dgr[4];
+    ldn(f, p0, pf);
+    ldn((const V*)dir, p0, pd);
+    ldn(a.sn, p0, psn);
+    ldn(a.se, p0, pse);
     const R dgh = a.dh[gj];
     R pss0 = R(0);
 #pragma unroll
-    for (int o = 0; o < 4; ++o) psw[o] = dgr[o] = R(0);
+    for (int o = 0; o < VWO; ++o) psw[o] = R(0);
+#pragma unroll
+    for (int o = 0; o < 4; ++o) dgr[o] = R(0);
     if (lane < 16) {
         if (gi0 > 0) pss0 = ldg<R>(a.sn, p0 - 1);
         else if (per) pss0 = ldg<R>(a.sn, (uint32_t)(nv - 1) + (uint32_t)nv * gj);
     }
     if (c == 0) {
-        if (gj > 0) ld4(a.se, p0 - (uint32_t)nv, psw);
+        if (gj > 0) ldn(a.se, p0 - (uint32_t)nv, psw);
         else if (per)
-            ld4(a.se, (uint32_t)gi0 + (uint32_t)nv * (uint32_t)(nh - 1), psw);
+            ldn(a.se, (uint32_t)gi0 + (uint32_t)nv * (uint32_t)(nh - 1), psw);
     }
     if (t < FY / 4) ld4(a.dv, (uint32_t)(i0 + 4 * t), dgr);
 
     // 2. the tile plus its halo of BW rows and columns, as units of VEC
     //    consecutive columns of one row, all loads in flight at once.  Unit
-    //    e = t + FT k sits at row ii = e mod RY, column VEC (e div RY);
+    //    e = t + NT k sits at row ii = e mod RY, column VEC (e div RY);
     //    interior tiles need no index map.
     R u[S::UPT][S::VEC];
     const bool inner = i0 >= BW && i0 + FY + BW <= nv && j0 >= BW &&
                        j0 + FX + BW <= nh;
     int ii = t % S::RY, jq = t / S::RY;
-    constexpr int DI = FT % S::RY, DJ = FT / S::RY;
+    constexpr int DI = NT % S::RY, DJ = NT / S::RY;
     if (inner) {
         const V* sb = src + (size_t)(i0 - BW) + (size_t)nv * (size_t)(j0 - BW);
 #pragma unroll
@@ -298,7 +369,7 @@ k_smooth_fine(FineArgs<R, V> a) {
             const uint32_t o = (uint32_t)ii + (uint32_t)nv * (uint32_t)(jq * S::VEC);
 #pragma unroll
             for (int cc = 0; cc < S::VEC; ++cc)
-                u[k][cc] = t + FT * k < S::NU
+                u[k][cc] = t + NT * k < S::NU
                                ? ldg<R>(sb, o + (uint32_t)nv * (uint32_t)cc)
                                : R(0);
             ii += DI;
@@ -312,7 +383,7 @@ k_smooth_fine(FineArgs<R, V> a) {
 #pragma unroll
             for (int cc = 0; cc < S::VEC; ++cc) {
                 u[k][cc] = R(0);
-                if (t + FT * k < S::NU) {
+                if (t + NT * k < S::NU) {
                     const int gjj =
                         fine_map(j0 - BW + jq * S::VEC + cc, nh, wraph);
                     u[k][cc] = ldg<R>(src, gi + (uint32_t)nv * (uint32_t)gjj);
@@ -334,7 +405,7 @@ k_smooth_fine(FineArgs<R, V> a) {
     }
 #pragma unroll
     for (int k = 0; k < S::UPT; ++k) {
-        const int e = t + FT * k;
+        const int e = t + NT * k;
         if (e < S::NU) {
             const int ii = e % S::RY, jq = e / S::RY;
             VT x;
@@ -350,8 +421,9 @@ k_smooth_fine(FineArgs<R, V> a) {
 
     // 3. horizontal pass over the tile's columns and every input row:
     //    ht(q, cc) = sum_k G_h(k) v(q, cc + k), k = 0..2BW
-    if (t < 2 * S::RY) {
-        const int hsel = t >= S::RY;
+    if (t < S::NH) {
+#pragma clang fp contract(off)
+        const int hsel = t / S::RY;
         const int q = t - hsel * S::RY;
         const int c0 = hsel * HWO;
         R w[S::HWL];
@@ -372,8 +444,9 @@ k_smooth_fine(FineArgs<R, V> a) {
     // 4. vertical pass for rows r0..r0+3 of column c
     R kv[VWO];
     {
+#pragma clang fp contract(off)
         R w[S::VWL];
-        lds_window<R, S::VWL>(ht + c * S::SH + r0, w);
+        lds_window<R, S::VWL, S::VCW>(ht + c * S::SH + r0, w);
 #pragma unroll
         for (int o = 0; o < VWO; ++o) kv[o] = tv[BW] * w[o + BW];
 #pragma unroll
@@ -397,29 +470,58 @@ k_smooth_fine(FineArgs<R, V> a) {
             if (c != 0) psw[o] = left;
         }
     }
-    R nd[4], nx[4];
-    double dot = 0.0;
+    R nd[VWO], nx[VWO];
+    double prod[VWO];
 #pragma unroll
     for (int o = 0; o < VWO; ++o) {
+        // Every fused multiply-add is written out and nothing else is fused,
+        // so both thread counts round every output the same way.
+#pragma clang fp contract(off)
         const R v = colv[o + 1];
         const R ss = o == 0 ? pss0 : psn[o - 1];
         const R sc = -(((psn[o] + ss) + pse[o]) + psw[o]);
-        R sv = sc * v;
-        sv += psn[o] * colv[o + 2];
-        sv += ss * colv[o];
-        sv += pse[o] * vc[o * S::SX + 1];
-        sv += psw[o] * vc[o * S::SX - 1];
-        const R kvo = kv[o] + l2 * sv;
-        const R dg = dgl[r0 + o] * dgh + l2 * sc;
-        nd[o] = cd * pd[o] + cr * (pf[o] - kvo) / dg;
+        R sv = fma(psn[o], colv[o + 2], sc * v);
+        sv = fma(ss, colv[o], sv);
+        sv = fma(pse[o], vc[o * S::SX + 1], sv);
+        sv = fma(psw[o], vc[o * S::SX - 1], sv);
+        const R kvo = fma(l2, sv, kv[o]);
+        const R dg = fma(dgl[r0 + o], dgh, l2 * sc);
+        nd[o] = fma(cd, pd[o], cr * (pf[o] - kvo) / dg);
         nx[o] = v + nd[o];
-        dot += (double)pf[o] * (double)nx[o];
+        // rounded product (never fused into the sum below: the lane that
+        // adds it may not be the lane that formed it)
+        prod[o] = __dmul_rn((double)pf[o], (double)nx[o]);
     }
-    st4(dir, p0, nd);
-    st4(out, p0, nx);
+    stn(dir, p0, nd);
+    stn(out, p0, nx);
     if (a.dot) {
-        const double s = block_sum<FT>(dot, red);
-        if (t == 0) a.part[(size_t)slot * a.part_stride + tile] = s;
+        // Partial of f . x_out over the tile in one order for both thread
+        // counts (so a slot's result does not depend on how many slots the
+        // launch has): the 1024 products go to LDS (over the input tile,
+        // which is no longer read), 256 threads each sum 4 consecutive rows
+        // of one column in row order, then a fixed tree.
+        static_assert(S::lds_bytes >= sizeof(double) * FY * FX,
+                      "room for the products");
+        __syncthreads();
+        double* pl = reinterpret_cast<double*>(lds_raw);
+#pragma unroll
+        for (int o = 0; o < VWO; ++o) pl[c * FY + r0 + o] = prod[o];
+        __syncthreads();
+        if (t < 256) {
+            const int cc = t & (FX - 1), rr = 4 * (t >> 4);
+            double dot = 0.0;
+#pragma unroll
+            for (int o = 0; o < 4; ++o)
+                dot = __dadd_rn(dot, pl[cc * FY + rr + o]);
+            red[t] = dot;
+        }
+        __syncthreads();
+#pragma unroll
+        for (int st = 128; st > 0; st >>= 1) {
+            if (t < st) red[t] += red[t + st];
+            __syncthreads();
+        }
+        if (t == 0) a.part[(size_t)slot * a.part_stride + tile] = red[0];
     }
 }
 
@@ -483,10 +585,15 @@ FineArgs<R, V> fine_args(const ApplyArgsT<R, V>& a, int bw) {
 
 template <class R, class V, int BW>
 void launch_fine(const ApplyArgsT<R, V>& a, hipStream_t s) {
-    using Sh = FineShape<R, BW>;
     dim3 grid(a.g.nv / FY, a.g.nh / FX, a.nslot);
-    hipLaunchKernelGGL((k_smooth_fine<R, V, BW>), grid, dim3(FT), Sh::lds_bytes,
-                       s, fine_args(a, BW));
+    if (a.nslot <= FWIDE_MAX)
+        hipLaunchKernelGGL((k_smooth_fine<R, V, BW, 512>), grid, dim3(512),
+                           (FineShape<R, BW, 512>::lds_bytes), s,
+                           fine_args(a, BW));
+    else
+        hipLaunchKernelGGL((k_smooth_fine<R, V, BW, 256>), grid, dim3(256),
+                           (FineShape<R, BW, 256>::lds_bytes), s,
+                           fine_args(a, BW));
 }
 
 template <class R, class V>

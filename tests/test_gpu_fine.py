@@ -10,7 +10,12 @@ kernel.  Checked on the same seeded inputs:
     RLS_FINE_KERNEL=generic: equal up to rounding (FP64 1e-12), and not
     bit-identical, which shows that the two problems ran different kernels
     (the tiled kernel adds symmetric tap pairs before multiplying);
-  * a sweep that uses it against the oracle's x*(lambda) (bar 1e-6).
+  * a sweep that uses it against the oracle's x*(lambda) (bar 1e-6);
+  * launches with one slot take 512-thread workgroups, more slots 256-thread
+    ones, with the same arithmetic per output and the same order of the
+    per-tile dot partials: a V-cycle on one lambda equals that lambda's slot
+    of a three-lambda V-cycle bitwise (and batched sweeps equal single-lambda
+    sweeps, tested with the sweeps).
 The cases cover band radii 2, 8 (padded from 6 in the other direction) and
 14 (the 15 x 15 PSF of the 512 x 512 workload), several tile rows and
 columns, both index maps, and four smoothing steps per level so that the
@@ -88,6 +93,17 @@ def test_tiled_vcycle_matches_general_kernel(name, monkeypatch):
     diff = np.abs(a - b).max() / np.abs(b).max()
     assert diff < 1e-12, (name, diff)
     assert diff > 0.0, name
+
+
+@pytest.mark.parametrize("name", list(CASES))
+def test_tiled_variants_agree_bitwise(name):
+    P, O, _ = _setup(name)
+    n = O.nv * O.nh
+    r = np.random.default_rng(12).standard_normal(len(LAMS) * n)
+    batch = host(P.vcycle(LAMS, dev(r))).reshape(len(LAMS), n)
+    for s in range(len(LAMS)):
+        one = host(P.vcycle(LAMS[s:s + 1], dev(r[s * n:(s + 1) * n])))
+        assert np.array_equal(one, batch[s]), (name, s)
 
 
 def test_tiled_sweep_matches_oracle():
