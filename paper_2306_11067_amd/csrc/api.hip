@@ -245,6 +245,11 @@ struct rls_problem {
     // RLS_FINE_KERNEL=generic at set-up: the finest-level Chebyshev step
     // always takes the general level-operator kernel
     int fine_generic = 0;
+    // measured workgroup size of the tiled finest-level Chebyshev kernel
+    // per slot count (0: not measured), for the FP64 and for the reduced-
+    // precision V-cycle
+    std::vector<int> fine_nt64 = std::vector<int>(FINE_ZMAX + 1, 0);
+    std::vector<int> fine_ntlo = std::vector<int>(FINE_ZMAX + 1, 0);
     int r_v = 0, r_h = 0;
     std::vector<double> taps_v, taps_h;
     std::vector<Level> lev;
@@ -325,13 +330,22 @@ void level_apply(int pro, int epi, const ApplyArgsT<R, V>& a, hipStream_t s) {
     }
 }
 
+// The launch arguments with the measured workgroup size for this slot count.
+template <class R, class V>
+ApplyArgsT<R, V> with_fine_nt(const std::vector<int>& tab,
+                              const ApplyArgsT<R, V>& a) {
+    ApplyArgsT<R, V> b = a;
+    if (a.nslot >= 1 && a.nslot <= FINE_ZMAX) b.fine_nt = tab[a.nslot];
+    return b;
+}
+
 void smooth_fine(rls_problem* P, const ApplyArgs& a, hipStream_t s) {
     if (a.g.ct.on) {
         launch_ct_apply(PRO_PLAIN, EPI_CHEB, a, s);
         return;
     }
     if (P->fine_generic) launch_apply(PRO_PLAIN, EPI_CHEB, a, s);
-    else launch_smooth_fine(a, s);
+    else launch_smooth_fine(with_fine_nt(P->fine_nt64, a), s);
     if (P->timer_on) P->run_cur.launches += 1;
 }
 // FP32 and BF16 V-cycles: not timed (the kernel timer covers the FP64
@@ -339,12 +353,12 @@ void smooth_fine(rls_problem* P, const ApplyArgs& a, hipStream_t s) {
 void smooth_fine(rls_problem* P, const ApplyArgsT<float>& a, hipStream_t s) {
     if (a.g.ct.on) launch_ct_apply(PRO_PLAIN, EPI_CHEB, a, s);
     else if (P->fine_generic) launch_apply(PRO_PLAIN, EPI_CHEB, a, s);
-    else launch_smooth_fine(a, s);
+    else launch_smooth_fine(with_fine_nt(P->fine_ntlo, a), s);
 }
 void smooth_fine(rls_problem* P, const ApplyArgsT<float, bf16>& a,
                  hipStream_t s) {
     if (P->fine_generic) launch_apply(PRO_PLAIN, EPI_CHEB, a, s);
-    else launch_smooth_fine(a, s);
+    else launch_smooth_fine(with_fine_nt(P->fine_ntlo, a), s);
 }
 
 void run_end(rls_problem* P, hipStream_t s) {
@@ -965,6 +979,88 @@ void vcycle(rls_problem* P, int k, int nslot, const int* slots,
     }
 }
 
+// Autotuning of the tiled finest-level Chebyshev kernel: for every slot
+// count a sweep can reach, time its 256- and 512-thread workgroups on the
+// V-cycle's (zeroed) workspace vectors and keep the faster.  The two sizes
+// give bit-identical results, so the choice only affects speed.  It runs
+// once per problem and slot count, at the start of a sweep, before any
+// graph capture; problems the tiled kernel does not serve are skipped.
+template <class V>
+rls_status tune_fine_t(rls_problem* P, std::vector<int>& tab, int nmax,
+                       hipStream_t s) {
+    using R = typename CompOf<V>::T;
+    Work& w = P->w;
+    nmax = std::min(nmax, FINE_ZMAX);
+    bool need = false;
+    for (int z = 1; z <= nmax; ++z) need = need || tab[z] == 0;
+    if (!need || P->fine_generic || P->is_ct) return RLS_OK;
+    const size_t n = (size_t)P->n();
+    V *in, *out, *d, *f;
+    if constexpr (std::is_same<V, double>::value) {
+        in = w.lxb[0].as<double>();
+        out = w.lt[0].as<double>();
+        d = w.ld[0].as<double>();
+        f = w.r.as<double>();
+    } else {
+        in = w.lxblo[0].as<V>();
+        out = w.zlo.as<V>();
+        d = w.ldlo[0].as<V>();
+        f = w.rlo.as<V>();
+    }
+    for (V* b : {in, out, d, f})
+        RLS_HIP(hipMemsetAsync(b, 0, sizeof(V) * (size_t)nmax * n, s));
+    ApplyArgsT<R, V> a;
+    a.g = P->lev[0].template geom_t<R>();
+    a.lam2 = w.lam2.as<double>();
+    a.in = in;
+    a.out = out;
+    a.d = d;
+    a.f = f;
+    a.cheb = w.cheb.as<double>();      // level 0, any step's coefficients
+    a.cheb_stride = 2 * P->nu_max;
+    hipEvent_t ev[2];
+    RLS_HIP(hipEventCreate(&ev[0]));
+    RLS_HIP(hipEventCreate(&ev[1]));
+    rls_status st = RLS_OK;
+    for (int z = 1; z <= nmax && st == RLS_OK; ++z) {
+        if (tab[z]) continue;
+        a.nslot = z;
+        float best[2] = {1e30f, 1e30f};
+        for (int rep = 0; rep < 3 && st == RLS_OK; ++rep) {
+            for (int v = 0; v < 2; ++v) {
+                a.fine_nt = v ? 512 : 256;
+                if (!launch_smooth_fine_tiled(a, s)) {   // not served
+                    std::fill(tab.begin(), tab.end(), 256);
+                    st = check_launch("tune_fine");
+                    break;
+                }
+                hipEventRecord(ev[0], s);
+                for (int k = 0; k < 4; ++k) launch_smooth_fine_tiled(a, s);
+                hipEventRecord(ev[1], s);
+                if (hipEventSynchronize(ev[1]) != hipSuccess) {
+                    st = fail(RLS_E_HIP, "tune_fine: event");
+                    break;
+                }
+                float ms = 0.f;
+                hipEventElapsedTime(&ms, ev[0], ev[1]);
+                best[v] = std::min(best[v], ms);
+            }
+            if (tab[z]) break;
+        }
+        if (st == RLS_OK && !tab[z]) tab[z] = best[1] < best[0] ? 512 : 256;
+    }
+    hipEventDestroy(ev[0]);
+    hipEventDestroy(ev[1]);
+    if (st != RLS_OK) return st;
+    return check_launch("tune_fine");
+}
+rls_status tune_fine(rls_problem* P, int nmax, hipStream_t s) {
+    if (P->prec == RLS_PREC_FP64) return tune_fine_t<double>(P, P->fine_nt64, nmax, s);
+    if (P->prec == RLS_PREC_MIXED_BF16)
+        return tune_fine_t<bf16>(P, P->fine_ntlo, nmax, s);
+    return tune_fine_t<float>(P, P->fine_ntlo, nmax, s);
+}
+
 // z = M r through the reduced-precision V-cycle with vectors of type V:
 // narrowing of r (after the convergence test when st is given), the
 // V-cycle, widening of z with the partials of r . z (and z . q).
@@ -1422,6 +1518,7 @@ rls_status rls_solve_sweep(rls_problem* p, const double* b, const double* lam,
     Work& w = p->w;
     RLS_TRY(upload_lam(p, lam, nlam, s));
     RLS_TRY(prepare_sweep(p, ns, s));
+    RLS_TRY(tune_fine(p, ns, s));
     double* part = w.part.as<double>();
     const int vb = vec_blocks(n);
     const LevelGeom g0 = p->lev[0].geom();

@@ -30,9 +30,10 @@ namespace {
 
 constexpr int FY = 64;    // output rows per tile (contiguous axis)
 constexpr int FX = 16;    // output columns per tile
-constexpr int FZ = 64;    // most slots per launch (the slot list is inline)
-// Launches with at most this many slots use 512-thread workgroups: with one
-// workgroup per CU the passes then run on two waves per SIMD.  Measured at
+constexpr int FZ = FINE_ZMAX;   // most slots per launch (inline slot list)
+// Without a measured choice (ApplyArgsT::fine_nt), launches with at most
+// this many slots use 512-thread workgroups: with one workgroup per CU the
+// passes then run on two waves per SIMD.  Measured at
 // 512 x 512, one PCG iteration with graph replay: one slot 2.54 ms against
 // 2.62 (FP64) and 2.36 against 2.39 (FP32 V-cycle); two slots 3.34 against
 // 3.39 (FP64) but 2.88 against 2.68 (FP32).
@@ -586,7 +587,8 @@ FineArgs<R, V> fine_args(const ApplyArgsT<R, V>& a, int bw) {
 template <class R, class V, int BW>
 void launch_fine(const ApplyArgsT<R, V>& a, hipStream_t s) {
     dim3 grid(a.g.nv / FY, a.g.nh / FX, a.nslot);
-    if (a.nslot <= FWIDE_MAX)
+    const int nt = a.fine_nt ? a.fine_nt : a.nslot <= FWIDE_MAX ? 512 : 256;
+    if (nt == 512)
         hipLaunchKernelGGL((k_smooth_fine<R, V, BW, 512>), grid, dim3(512),
                            (FineShape<R, BW, 512>::lds_bytes), s,
                            fine_args(a, BW));

@@ -159,6 +159,9 @@ struct SlotState {
 // Slot lists up to this length also travel in the kernel arguments (read
 // through the scalar kernel-argument path instead of a global load).
 constexpr int ZINLINE = 32;
+// Most slots in one launch of the tiled finest-level Chebyshev kernel (its
+// slot list is inline).
+constexpr int FINE_ZMAX = 64;
 
 // Arguments of the level-operator kernel; R is the arithmetic type and the
 // type of the level's bands and stencil (double, or float for the FP32 and
@@ -200,6 +203,9 @@ struct ApplyArgsT {
     int gate = 0;                    // convergence test before the V-cycle
     const double* part_rr = nullptr; // gate: partials of ||r||^2
     int nrr = 0;
+    // threads per workgroup of the tiled finest-level Chebyshev kernel
+    // (256 or 512, both giving the same results; 0: built-in rule)
+    int fine_nt = 0;
 };
 using ApplyArgs = ApplyArgsT<double>;
 
