@@ -979,12 +979,15 @@ void vcycle(rls_problem* P, int k, int nslot, const int* slots,
     }
 }
 
-// Autotuning of the tiled finest-level Chebyshev kernel: for every slot
-// count a sweep can reach, time its 256- and 512-thread workgroups on the
-// V-cycle's (zeroed) workspace vectors and keep the faster.  The two sizes
-// give bit-identical results, so the choice only affects speed.  It runs
-// once per problem and slot count, at the start of a sweep, before any
-// graph capture; problems the tiled kernel does not serve are skipped.
+// Autotuning of the tiled finest-level Chebyshev kernel: for the slot
+// counts a sweep can reach, in increasing order, time its 256- and
+// 512-thread workgroups on the V-cycle's (zeroed) workspace vectors and keep
+// the faster; once 256 threads have won at two consecutive counts, larger
+// counts take 256 without timing (more slots only add workgroups per CU,
+// which favours the smaller size).  The two sizes give bit-identical
+// results, so the choice only affects speed.  It runs once per problem and
+// slot count, at the start of a sweep, before any graph capture; problems
+// the tiled kernel does not serve are skipped.
 template <class V>
 rls_status tune_fine_t(rls_problem* P, std::vector<int>& tab, int nmax,
                        hipStream_t s) {
@@ -1022,8 +1025,16 @@ rls_status tune_fine_t(rls_problem* P, std::vector<int>& tab, int nmax,
     RLS_HIP(hipEventCreate(&ev[0]));
     RLS_HIP(hipEventCreate(&ev[1]));
     rls_status st = RLS_OK;
+    int wins256 = 0;   // consecutive slot counts where 256 threads won
     for (int z = 1; z <= nmax && st == RLS_OK; ++z) {
-        if (tab[z]) continue;
+        if (tab[z]) {
+            wins256 = tab[z] == 256 ? wins256 + 1 : 0;
+            continue;
+        }
+        if (wins256 >= 2) {   // larger launches only favour 256 threads more
+            tab[z] = 256;
+            continue;
+        }
         a.nslot = z;
         float best[2] = {1e30f, 1e30f};
         for (int rep = 0; rep < 3 && st == RLS_OK; ++rep) {
@@ -1048,6 +1059,7 @@ rls_status tune_fine_t(rls_problem* P, std::vector<int>& tab, int nmax,
             if (tab[z]) break;
         }
         if (st == RLS_OK && !tab[z]) tab[z] = best[1] < best[0] ? 512 : 256;
+        wins256 = tab[z] == 256 ? wins256 + 1 : 0;
     }
     hipEventDestroy(ev[0]);
     hipEventDestroy(ev[1]);

@@ -38,7 +38,7 @@ constexpr int FZ = FINE_ZMAX;   // most slots per launch (inline slot list)
 // 2.62 (FP64) and 2.36 against 2.39 (FP32 V-cycle); two slots 3.34 against
 // 3.39 (FP64) but 2.88 against 2.68 (FP32).
 constexpr int FWIDE_MAX = 1;
-constexpr int FBW = 16;   // largest band radius with a specialised kernel
+constexpr int FBW = 20;   // largest band radius with a specialised kernel
 
 template <class R>
 struct Vec16;
@@ -584,8 +584,29 @@ FineArgs<R, V> fine_args(const ApplyArgsT<R, V>& a, int bw) {
     return f;
 }
 
+// Dynamic LDS beyond the default 64 KiB needs the kernel attribute (the
+// widest FP64 instances: 61 KiB of tile plus 4 KiB of static LDS).
+template <class R, class V, int BW, int NT>
+void allow_fine_lds() {
+    static const bool done = [] {
+        const void* fn = (const void*)k_smooth_fine<R, V, BW, NT>;
+        hipFuncAttributes attr;
+        size_t stat = 0;
+        if (hipFuncGetAttributes(&attr, fn) == hipSuccess)
+            stat = attr.sharedSizeBytes;
+        (void)hipFuncSetAttribute(fn,
+                                  hipFuncAttributeMaxDynamicSharedMemorySize,
+                                  (int)(160 * 1024 - stat));
+        (void)hipGetLastError();
+        return true;
+    }();
+    (void)done;
+}
+
 template <class R, class V, int BW>
 void launch_fine(const ApplyArgsT<R, V>& a, hipStream_t s) {
+    allow_fine_lds<R, V, BW, 256>();
+    allow_fine_lds<R, V, BW, 512>();
     dim3 grid(a.g.nv / FY, a.g.nh / FX, a.nslot);
     const int nt = a.fine_nt ? a.fine_nt : a.nslot <= FWIDE_MAX ? 512 : 256;
     if (nt == 512)
@@ -609,6 +630,8 @@ bool fine_impl(const ApplyArgsT<R, V>& a, hipStream_t s) {
         case 12: launch_fine<R, V, 12>(a, s); return true;
         case 14: launch_fine<R, V, 14>(a, s); return true;
         case 16: launch_fine<R, V, 16>(a, s); return true;
+        case 18: launch_fine<R, V, 18>(a, s); return true;
+        case 20: launch_fine<R, V, 20>(a, s); return true;
         default: return false;
     }
 }
