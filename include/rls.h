@@ -289,6 +289,68 @@ rls_status rls_apply_forward(rls_problem* p, const double* x, double* y,
 rls_status rls_apply_adjoint(rls_problem* p, const double* y, double* x,
                              int nvec, void* stream);
 
+/* ---------------------------------------------------------------------
+ * Outer reweighting loop (paper Algorithm 2, Section 3.6).
+ * ------------------------------------------------------------------- */
+
+/* Weight update of eq. (g) (paper Section 2) from a solution x (device, n
+ * values): with w = |D L x| over the 2n gradient entries (L the forward
+ * differences of the problem's gradient, D its current weights),
+ * g = w / ||w||_inf and D <- diag(1 - g^q) D; then the per-weighting
+ * set-up for the new D, as rls_set_weights does.  ||w||_inf = 0 leaves D
+ * unchanged.  gmax: host, receives ||w||_inf (may be NULL).  Synchronous.
+ * Errors: RLS_E_STATE, RLS_E_ARG (null x, q <= 0 or non-finite), RLS_E_OOM,
+ * RLS_E_HIP. */
+rls_status rls_update_weights(rls_problem* p, const double* x, double q,
+                              double* gmax, void* stream);
+
+/* Copy of the current weights D (2n values, vertical plane first) into d
+ * (device); ones for D = I.  Errors: RLS_E_STATE, RLS_E_ARG, RLS_E_HIP. */
+rls_status rls_get_weights(const rls_problem* p, double* d, void* stream);
+
+/* L-curve corner (paper Section 1, the criterion of Hansen and O'Leary):
+ * natural cubic splines of log10 rho and log10 eta over log10 lambda
+ * through the m points, their curvature sampled 64 times per interval, and
+ * *index = the point nearest, in the log-log plane, to the sample of
+ * largest curvature.  lam, rho, eta: host, m values, positive and finite,
+ * lam strictly increasing.  Host only, no GPU work.
+ * Errors: RLS_E_ARG (m < 3, null pointers, values out of range). */
+rls_status rls_lcurve_corner(const double* lam, const double* rho,
+                             const double* eta, int m, int* index);
+
+/* Pruned lambda range of paper Section 3.4 (0-based, inclusive): ten
+ * indices from i_prev - 2 to i_prev + 7, shifted to the first or last ten
+ * near the ends.  Errors: RLS_E_ARG (m < 10, i_prev out of range). */
+rls_status rls_trim_window(int i_prev, int m, int* lo, int* hi);
+
+/* Outcome of rls_regularize. */
+typedef struct {
+    int outer;          /* outer iterations run                              */
+    int stopped;        /* 1: the stopping rule of Section 3.5 fired         */
+    int chosen_index;   /* lambda index of the returned solution            */
+    long long iters;    /* PCG iterations summed over all solves             */
+} rls_outer_info;
+
+/* Algorithm 2: starting from D = I, outer iteration l solves every lambda
+ * (l = 1) or the pruned range around the previous choice (rls_trim_window)
+ * with rls_solve_sweep, picks the corner lambda (rls_lcurve_corner), stops
+ * once the same index was picked three times in a row (Section 3.5), and
+ * otherwise updates D from the chosen solution (rls_update_weights).  Each
+ * lambda's solve starts from that lambda's latest solution (zero at first).
+ * b: device, the data.  lam: host, m >= 10 values, positive, strictly
+ * increasing.  q > 0: the exponent of eq. (g).  tol, opts: as in
+ * rls_solve_sweep.  chosen: host, maxouter ints, the index picked at each
+ * outer iteration.  x: device, n values, the solution at the last pick.
+ * The library allocates m n doubles of device memory for the solutions
+ * while it runs; on return the problem holds the weights of the last
+ * solve.  Synchronous.  Errors: RLS_E_STATE, RLS_E_ARG, and those of
+ * rls_solve_sweep. */
+rls_status rls_regularize(rls_problem* p, const double* b, const double* lam,
+                          int m, double q, double tol,
+                          const rls_sweep_opts* opts, int maxouter,
+                          int* chosen, double* x, rls_outer_info* info,
+                          void* stream);
+
 #ifdef __cplusplus
 }
 #endif

@@ -86,8 +86,8 @@ def stop_rule(chosen):
 def regularize(make_oracle, b, lam, q, maxouter, nv, nh, lbc):
     """Algorithm 2 with exact solves.  make_oracle(d) returns the oracle
     object (DeblurOracle or CtOracle) for weights d.  Returns the chosen
-    solution, the chosen indices per outer iteration, the final weights and
-    whether the stopping rule fired."""
+    solution, the chosen indices per outer iteration, the weights of the
+    last solve (None for D = I) and whether the stopping rule fired."""
     lam = np.asarray(lam, float)
     m = len(lam)
     d = None
@@ -103,6 +103,7 @@ def regularize(make_oracle, b, lam, q, maxouter, nv, nh, lbc):
         x_star = xs[c]
         if stop_rule(chosen):
             return x_star, chosen, d, True
-        d_prev = np.ones(2 * nv * nh) if d is None else d
-        d, _ = weight_update(d_prev, x_star, nv, nh, lbc, q)
+        if ell + 1 < maxouter:
+            d_prev = np.ones(2 * nv * nh) if d is None else d
+            d, _ = weight_update(d_prev, x_star, nv, nh, lbc, q)
     return x_star, chosen, d, False

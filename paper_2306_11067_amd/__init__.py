@@ -121,6 +121,40 @@ class Problem:
                     relres_true=i.relres_true) for i in info]
         return x.view(nl, self.n), res, sem, inf
 
+    # ---------------------------------------------------- outer loop ABI
+    def update_weights(self, x, q):
+        """eq. (g) from the solution x (device, n values); returns
+        ||D L x||_inf."""
+        top = C.c_double()
+        _check(self._lib.rls_update_weights(self._h, _dptr(x, "x", self.n),
+                                            float(q), C.byref(top), _stream()))
+        return top.value
+
+    def weights(self):
+        import torch
+        out = torch.empty(2 * self.n, dtype=torch.float64, device="cuda")
+        _check(self._lib.rls_get_weights(self._h, _dptr(out, "d"), _stream()))
+        return out
+
+    def regularize(self, b, lams, q, tol, maxouter=10, maxit=100000,
+                   tol_mode="relative", poll_every=32, graph=True):
+        """Algorithm 2; returns (x, chosen indices, info dict)."""
+        import torch
+        lam, plam = _dbl(lams)
+        opts = L.SweepOpts(int(maxit), L.RLS_TOL_ABSOLUTE if tol_mode ==
+                           "absolute" else L.RLS_TOL_RELATIVE, int(poll_every),
+                           1 if graph else 0)
+        chosen = (C.c_int * int(maxouter))()
+        info = L.OuterInfo()
+        x = torch.empty(self.n, dtype=torch.float64, device=b.device)
+        _check(self._lib.rls_regularize(
+            self._h, _dptr(b, "b", self.m), plam, len(lam), float(q),
+            float(tol), C.byref(opts), int(maxouter), chosen, _dptr(x, "x"),
+            C.byref(info), _stream()))
+        return x, list(chosen)[:info.outer], dict(
+            outer=info.outer, stopped=bool(info.stopped),
+            chosen_index=info.chosen_index, iters=info.iters)
+
     # ------------------------------------------------------------ step ABI
     def level_shape(self, level):
         a, b = C.c_int(), C.c_int()
@@ -230,6 +264,24 @@ class TomographyProblem(Problem):
         _check(self._lib.rls_setup(C.byref(h), C.byref(op), C.byref(g), d,
                                    _stream()))
         self._h = h
+
+
+def lcurve_corner(lams, rho, eta):
+    """Index of the L-curve corner (host computation in the library)."""
+    lam, plam = _dbl(lams)
+    r, pr = _dbl(rho)
+    e, pe = _dbl(eta)
+    idx = C.c_int()
+    _check(L.load().rls_lcurve_corner(plam, pr, pe, len(lam), C.byref(idx)))
+    return idx.value
+
+
+def trim_window(i_prev, m):
+    """Inclusive (lo, hi) of the pruned lambda range."""
+    lo, hi = C.c_int(), C.c_int()
+    _check(L.load().rls_trim_window(int(i_prev), int(m), C.byref(lo),
+                                    C.byref(hi)))
+    return lo.value, hi.value
 
 
 def solve_batch(entries):

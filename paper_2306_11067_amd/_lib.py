@@ -36,7 +36,9 @@ EXPORTS = [
     "rls_last_error", "rls_level_shape", "rls_apply_normal", "rls_vcycle",
     "rls_get_stencil", "rls_get_gram_band", "rls_gershgorin",
     "rls_apply_forward", "rls_apply_adjoint", "rls_kernel_timer",
-    "rls_kernel_timer_read", "rls_solve_batch",
+    "rls_kernel_timer_read", "rls_solve_batch", "rls_update_weights",
+    "rls_get_weights", "rls_lcurve_corner", "rls_trim_window",
+    "rls_regularize",
 ]
 
 
@@ -67,6 +69,11 @@ class SolveInfo(C.Structure):
 
 _P = C.c_void_p
 _D = C.POINTER(C.c_double)
+
+
+class OuterInfo(C.Structure):
+    _fields_ = [("outer", C.c_int), ("stopped", C.c_int),
+                ("chosen_index", C.c_int), ("iters", C.c_longlong)]
 
 
 class Sweep(C.Structure):
@@ -102,6 +109,16 @@ def _declare(lib):
     lib.rls_kernel_timer_read.argtypes = [_P, C.POINTER(C.c_longlong),
                                           C.POINTER(C.c_double),
                                           C.POINTER(C.c_double)]
+    lib.rls_update_weights.argtypes = [_P, _P, C.c_double, _D, _P]
+    lib.rls_get_weights.argtypes = [_P, _P, _P]
+    lib.rls_lcurve_corner.argtypes = [_D, _D, _D, C.c_int,
+                                      C.POINTER(C.c_int)]
+    lib.rls_trim_window.argtypes = [C.c_int, C.c_int, C.POINTER(C.c_int),
+                                    C.POINTER(C.c_int)]
+    lib.rls_regularize.argtypes = [_P, _P, _D, C.c_int, C.c_double,
+                                   C.c_double, C.POINTER(SweepOpts), C.c_int,
+                                   C.POINTER(C.c_int), _P,
+                                   C.POINTER(OuterInfo), _P]
     for name in EXPORTS:
         if name not in ("rls_destroy", "rls_last_error"):
             getattr(lib, name).restype = C.c_int
@@ -119,5 +136,10 @@ def load():
             raise RuntimeError(
                 f"{LIB_PATH} is missing: build it with "
                 "`python -m paper_2306_11067_amd.build` (hipcc, gfx950)")
+        # torch ships its own HIP runtime; load it first so that the
+        # library's HIP dependency resolves to the runtime torch uses (a
+        # second runtime in the process finds no device once torch has
+        # opened it)
+        import torch  # noqa: F401
         _lib = _declare(C.CDLL(LIB_PATH))
     return _lib

@@ -12,6 +12,7 @@
 #include <type_traits>
 #include <vector>
 
+#include "outer.h"
 #include "rls_internal.h"
 
 using namespace rls;
@@ -1343,6 +1344,148 @@ rls_status rls_set_weights(rls_problem* p, const double* d, void* stream) {
     hipStream_t s = (hipStream_t)stream;
     RLS_TRY(install_weights(p, d, s));
     RLS_HIP(hipStreamSynchronize(s));
+    return RLS_OK;
+}
+
+namespace {
+
+// eq. (g) on the problem's own weights: D <- diag(1 - (|D L x| /
+// ||D L x||_inf)^q) D, then the per-weighting set-up (stencils of every
+// level) for the new D.
+rls_status update_weights(rls_problem* P, const double* x, double q,
+                          double* top_host, hipStream_t s) {
+    const int64_t n = P->n();
+    DBuf part, dnew, top;
+    RLS_TRY(dalloc(part, sizeof(double) * weight_update_parts()));
+    RLS_TRY(dalloc(dnew, sizeof(double) * 2 * n));
+    RLS_TRY(dalloc(top, sizeof(double)));
+    launch_weight_update(x, P->unit_weights ? nullptr : P->weights.as<double>(),
+                         P->nv, P->nh, P->periodic, q, part.as<double>(),
+                         dnew.as<double>(), top.as<double>(), s);
+    RLS_TRY(check_launch("weight update"));
+    RLS_TRY(install_weights(P, dnew.as<double>(), s));
+    if (top_host)
+        RLS_HIP(hipMemcpyAsync(top_host, top.p, sizeof(double),
+                               hipMemcpyDeviceToHost, s));
+    RLS_HIP(hipStreamSynchronize(s));
+    return RLS_OK;
+}
+
+rls_status check_lcurve(const double* lam, const double* rho,
+                        const double* eta, int m) {
+    if (!lam || !rho || !eta) return fail(RLS_E_ARG, "null L-curve array");
+    if (m < 3) return fail(RLS_E_ARG, "the L-curve needs at least 3 points");
+    for (int i = 0; i < m; ++i) {
+        if (!(std::isfinite(lam[i]) && lam[i] > 0 && std::isfinite(rho[i]) &&
+              rho[i] > 0 && std::isfinite(eta[i]) && eta[i] > 0))
+            return fail(RLS_E_ARG, "lambda, residual and seminorm must be "
+                                   "positive and finite");
+        if (i && !(lam[i] > lam[i - 1]))
+            return fail(RLS_E_ARG, "lambdas must be strictly increasing");
+    }
+    return RLS_OK;
+}
+
+}  // namespace
+
+rls_status rls_update_weights(rls_problem* p, const double* x, double q,
+                              double* gmax, void* stream) {
+    g_last_error.clear();
+    if (!p) return fail(RLS_E_STATE, "null handle");
+    if (!x) return fail(RLS_E_ARG, "null x");
+    if (!(std::isfinite(q) && q > 0)) return fail(RLS_E_ARG, "q must be > 0");
+    return update_weights(p, x, q, gmax, (hipStream_t)stream);
+}
+
+rls_status rls_get_weights(const rls_problem* p, double* d, void* stream) {
+    g_last_error.clear();
+    if (!p) return fail(RLS_E_STATE, "null handle");
+    if (!d) return fail(RLS_E_ARG, "null d");
+    hipStream_t s = (hipStream_t)stream;
+    const int64_t n2 = 2 * p->n();
+    if (p->unit_weights) {
+        std::vector<double> ones(n2, 1.0);
+        RLS_HIP(hipMemcpyAsync(d, ones.data(), sizeof(double) * n2,
+                               hipMemcpyHostToDevice, s));
+    } else {
+        RLS_HIP(hipMemcpyAsync(d, p->weights.p, sizeof(double) * n2,
+                               hipMemcpyDeviceToDevice, s));
+    }
+    RLS_HIP(hipStreamSynchronize(s));
+    return RLS_OK;
+}
+
+rls_status rls_lcurve_corner(const double* lam, const double* rho,
+                             const double* eta, int m, int* index) {
+    g_last_error.clear();
+    if (!index) return fail(RLS_E_ARG, "null index");
+    RLS_TRY(check_lcurve(lam, rho, eta, m));
+    *index = lcurve_corner_host(lam, rho, eta, m);
+    return RLS_OK;
+}
+
+rls_status rls_trim_window(int i_prev, int m, int* lo, int* hi) {
+    g_last_error.clear();
+    if (!lo || !hi) return fail(RLS_E_ARG, "null output");
+    if (m < TRIM_SIZE) return fail(RLS_E_ARG, "pruning needs at least 10 lambdas");
+    if (i_prev < 0 || i_prev >= m) return fail(RLS_E_ARG, "index out of range");
+    trim_window_host(i_prev, m, lo, hi);
+    return RLS_OK;
+}
+
+rls_status rls_regularize(rls_problem* p, const double* b, const double* lam,
+                          int m, double q, double tol,
+                          const rls_sweep_opts* opts, int maxouter,
+                          int* chosen, double* x, rls_outer_info* info,
+                          void* stream) {
+    g_last_error.clear();
+    if (!p) return fail(RLS_E_STATE, "null handle");
+    if (!b || !lam || !x || !chosen) return fail(RLS_E_ARG, "null argument");
+    if (m < TRIM_SIZE) return fail(RLS_E_ARG, "Algorithm 2 needs at least 10 lambdas");
+    if (maxouter < 1) return fail(RLS_E_ARG, "maxouter must be >= 1");
+    if (!(std::isfinite(q) && q > 0)) return fail(RLS_E_ARG, "q must be > 0");
+    for (int i = 0; i < m; ++i)
+        if (!(std::isfinite(lam[i]) && lam[i] > 0) || (i && !(lam[i] > lam[i - 1])))
+            return fail(RLS_E_ARG, "lambdas must be positive, finite and "
+                                   "strictly increasing");
+    hipStream_t s = (hipStream_t)stream;
+    const int64_t n = p->n();
+    // every lambda's latest solution: the warm start of its next solve
+    DBuf xall;
+    RLS_TRY(dalloc(xall, sizeof(double) * (size_t)m * n));
+    RLS_HIP(hipMemsetAsync(xall.p, 0, sizeof(double) * (size_t)m * n, s));
+    RLS_TRY(install_weights(p, nullptr, s));           // D = I
+    std::vector<double> res(m), sem(m);
+    std::vector<rls_solve_info> sinfo(m);
+    rls_outer_info out{};
+    int stopped = 0, ell = 0, pick = 0;
+    for (; ell < maxouter && !stopped; ++ell) {
+        int lo = 0, hi = m - 1;
+        if (ell) trim_window_host(chosen[ell - 1], m, &lo, &hi);
+        const int cnt = hi - lo + 1;
+        double* xs = xall.as<double>() + (size_t)lo * n;
+        RLS_TRY(rls_solve_sweep(p, b, lam + lo, cnt, tol, opts, xs, xs,
+                                res.data(), sem.data(), sinfo.data(), stream));
+        for (int i = 0; i < cnt; ++i) out.iters += sinfo[i].iters;
+        for (int i = 0; i < cnt; ++i)
+            if (!(res[i] > 0 && sem[i] > 0 && std::isfinite(res[i]) &&
+                  std::isfinite(sem[i])))
+                return fail(RLS_E_ARG, "a sweep returned a zero or non-finite "
+                                       "L-curve point");
+        pick = lo + lcurve_corner_host(lam + lo, res.data(), sem.data(), cnt);
+        chosen[ell] = pick;
+        stopped = ell >= 2 && chosen[ell - 2] == pick && chosen[ell - 1] == pick;
+        if (!stopped && ell + 1 < maxouter)
+            RLS_TRY(update_weights(p, xall.as<double>() + (size_t)pick * n, q,
+                                   nullptr, s));
+    }
+    RLS_HIP(hipMemcpyAsync(x, xall.as<double>() + (size_t)pick * n,
+                           sizeof(double) * n, hipMemcpyDeviceToDevice, s));
+    RLS_HIP(hipStreamSynchronize(s));
+    out.outer = ell;
+    out.stopped = stopped;
+    out.chosen_index = pick;
+    if (info) *info = out;
     return RLS_OK;
 }
 

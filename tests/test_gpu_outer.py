@@ -1,0 +1,119 @@
+"""The outer reweighting loop (Algorithm 2) on the GPU against the oracle.
+
+  * rls_update_weights (eq. (g)) on Neumann and periodic grids, with D = I
+    and with stored weights, for q = 1, 2 and 0.7, on a grid whose 2n
+    gradient entries are not a whole number of 256-thread blocks and on a
+    512 x 512 grid (more blocks than the maximum pass launches, so its
+    grid-stride loop runs): the new weights within 1e-13 absolute of the
+    oracle's (the oracle forms D L as a sparse product, -d x_k + d x_{k+1},
+    the kernel d (x_{k+1} - x_k): a few FP64 roundings of the entry, divided
+    by ||D L x||_inf, which is of the order of the entries here), and
+    ||D L x||_inf within 1e-14 relative;
+  * a flat image leaves D bitwise unchanged and reports ||D L x||_inf = 0;
+  * two updates in a row match the oracle's chain;
+  * rls_regularize on a 64 x 64 reflective deblurring problem with 16
+    lambdas in [1e-4, 1] and q = 2: the same index at every outer iteration
+    and the same stop as the oracle's Algorithm 2 with exact solves, the
+    returned solution within 1e-6 of the oracle's, and the final weights
+    within 1e-6 (each update sees a solution with the solver's error).
+"""
+import numpy as np
+import pytest
+
+import workloads as W
+from oracle import outer
+from oracle.pcg import DeblurOracle
+from tests.gpu_util import dev, host
+
+pytestmark = pytest.mark.gpu
+
+GRIDS = {
+    # name: (nv, nh, lbc, bc, levels)
+    "neumann92x76": (92, 76, "neumann", "reflective", 3),
+    "periodic64x48": (64, 48, "periodic", "periodic", 3),
+    "neumann512": (512, 512, "neumann", "reflective", 5),
+}
+
+
+def _problem(nv, nh, lbc, bc, levels, d=None):
+    from paper_2306_11067_amd import Problem
+    taps = W.gaussian_taps(2, 1.0)
+    return Problem(nv, nh, taps, taps, bc, lbc, levels,
+                   weights=None if d is None else dev(d))
+
+
+def _image(nv, nh, rng):
+    i = np.arange(nv)[None, :]
+    j = np.arange(nh)[:, None]
+    smooth = np.sin(2 * np.pi * i / nv) * np.cos(2 * np.pi * j / nh)
+    return (smooth + 0.3 * rng.standard_normal((nh, nv))).ravel()
+
+
+@pytest.mark.parametrize("q", [1.0, 2.0, 0.7])
+@pytest.mark.parametrize("unit", [True, False])
+@pytest.mark.parametrize("name", list(GRIDS))
+def test_weight_update_matches_oracle(name, unit, q):
+    nv, nh, lbc, bc, levels = GRIDS[name]
+    rng = np.random.default_rng(31)
+    n = nv * nh
+    d0 = np.ones(2 * n) if unit else rng.uniform(0.01, 1.0, 2 * n)
+    P = _problem(nv, nh, lbc, bc, levels, None if unit else d0)
+    x = _image(nv, nh, rng)
+    top = P.update_weights(dev(x), q)
+    got = host(P.weights())
+    want, wtop = outer.weight_update(d0, x, nv, nh, lbc, q)
+    assert abs(top - wtop) <= 1e-14 * wtop, (top, wtop)
+    err = np.abs(got - want).max()
+    assert err <= 1e-13, (name, unit, q, err)
+    assert np.count_nonzero(got == 0.0) >= 1
+    P.close()
+
+
+def test_flat_image_keeps_weights_bitwise():
+    nv, nh, lbc, bc, levels = GRIDS["neumann92x76"]
+    d0 = np.random.default_rng(2).uniform(0.01, 1.0, 2 * nv * nh)
+    P = _problem(nv, nh, lbc, bc, levels, d0)
+    top = P.update_weights(dev(np.full(nv * nh, 0.25)), 2.0)
+    assert top == 0.0
+    assert np.array_equal(host(P.weights()), d0)
+    P.close()
+
+
+def test_two_updates_match_oracle_chain():
+    nv, nh, lbc, bc, levels = GRIDS["periodic64x48"]
+    rng = np.random.default_rng(4)
+    P = _problem(nv, nh, lbc, bc, levels)
+    d = np.ones(2 * nv * nh)
+    for q in (2.0, 1.0):
+        x = _image(nv, nh, rng)
+        P.update_weights(dev(x), q)
+        d, _ = outer.weight_update(d, x, nv, nh, lbc, q)
+    assert np.abs(host(P.weights()) - d).max() <= 1e-13
+    P.close()
+
+
+def test_regularize_matches_oracle_algorithm():
+    from paper_2306_11067_amd import Problem
+    P_ = W.small_deblur(64, 64, 3, 1.5, "reflective", "neumann", 3, nlam=16)
+    q, maxouter = 2.0, 12
+    n = P_.nv * P_.nh
+
+    def make(d):
+        return DeblurOracle(P_.nv, P_.nh, P_.taps_v, P_.taps_h, P_.bc, P_.lbc,
+                            np.ones(2 * n) if d is None else d, 1)
+
+    xw, chosen_w, dw, stopped_w = outer.regularize(
+        make, P_.b, P_.lams, q, maxouter, P_.nv, P_.nh, P_.lbc)
+    prob = Problem(P_.nv, P_.nh, P_.taps_v, P_.taps_h, P_.bc, P_.lbc,
+                   P_.levels)
+    x, chosen, info = prob.regularize(dev(P_.b), P_.lams, q, 1e-12,
+                                      maxouter=maxouter)
+    assert chosen == chosen_w, (chosen, chosen_w)
+    assert info["stopped"] == stopped_w
+    assert info["chosen_index"] == chosen_w[-1]
+    xg = host(x)
+    assert np.linalg.norm(xg - xw) <= 1e-6 * np.linalg.norm(xw)
+    dg = host(prob.weights())
+    dref = np.ones(2 * n) if dw is None else dw
+    assert np.abs(dg - dref).max() <= 1e-6
+    prob.close()
