@@ -15,15 +15,21 @@
     lambdas in [1e-4, 1] and q = 2: the same index at every outer iteration
     and the same stop as the oracle's Algorithm 2 with exact solves, the
     returned solution within 1e-6 of the oracle's, and the final weights
-    within 1e-6 (each update sees a solution with the solver's error).
+    within 1e-6 (each update sees a solution with the solver's error);
+  * rls_regularize on a 32 x 32 tomography problem (24 angles, 12 lambdas
+    in [1e-3, 1e2], FP32 V-cycle under FP64 PCG), six outer iterations: the
+    same choices as the oracle's dense solves (the closest call among them
+    has the nearest point 11 % nearer to the corner than the next), solution
+    and weights within 1e-6.
 """
 import numpy as np
 import pytest
 
 import workloads as W
 from oracle import outer
-from oracle.pcg import DeblurOracle
+from oracle.pcg import CtOracle, DeblurOracle
 from tests.gpu_util import dev, host
+from workloads.ct import small_ct
 
 pytestmark = pytest.mark.gpu
 
@@ -116,4 +122,29 @@ def test_regularize_matches_oracle_algorithm():
     dg = host(prob.weights())
     dref = np.ones(2 * n) if dw is None else dw
     assert np.abs(dg - dref).max() <= 1e-6
+    prob.close()
+
+
+def test_regularize_tomography_matches_oracle_algorithm():
+    from paper_2306_11067_amd import TomographyProblem
+    P = small_ct(32, 24, 3, 12)
+    A = P.matrix()
+    q, maxouter = 2.0, 6
+    n = P.N * P.N
+
+    def make(d):
+        return CtOracle(A, P.N, P.lbc, np.ones(2 * n) if d is None else d, 1)
+
+    xw, chosen_w, dw, stopped_w = outer.regularize(
+        make, P.b, P.lams, q, maxouter, P.N, P.N, P.lbc)
+    prob = TomographyProblem(P.rowptr, P.col, P.val, P.N, 3, nu=4,
+                             cheb_ratio=16.0)
+    x, chosen, info = prob.regularize(dev(P.b), P.lams, q, 1e-13,
+                                      maxouter=maxouter, poll_every=8)
+    assert chosen == chosen_w, (chosen, chosen_w)
+    assert info["stopped"] == stopped_w
+    xg = host(x)
+    assert np.linalg.norm(xg - xw) <= 1e-6 * np.linalg.norm(xw)
+    dref = np.ones(2 * n) if dw is None else dw
+    assert np.abs(host(prob.weights()) - dref).max() <= 1e-6
     prob.close()
