@@ -106,7 +106,10 @@ typedef struct {
     int r_v, r_h;           /* tap radii: 2r+1 taps per direction            */
     const double* taps_v;   /* host, 2*r_v+1 values, t_{-r}..t_{r}           */
     const double* taps_h;   /* host, 2*r_h+1 values                          */
-    /* general sparse (not supported by this build: RLS_E_UNSUPPORTED) */
+    /* general sparse A (RLS_OP_CSR, e.g. a tomography projector): m rows
+     * over the n = nv*nh pixels, rows sorted by column, values >= 0; runs
+     * with RLS_PREC_MIXED_FP32 only; at most 512 nonzeros per row and 4096
+     * per column (the on-GPU hierarchy build) */
     int64_t m, nnz;
     const int64_t* rowptr;  /* host, m+1 */
     const int32_t* col;     /* host, nnz */
@@ -159,7 +162,10 @@ typedef struct rls_problem rls_problem;
  * RLS_FINE_KERNEL=generic, read here, makes this problem use the general
  * level-operator kernel instead (same arithmetic up to rounding).
  * Errors: RLS_E_ARG (bad sizes, radii >= n/2, non-finite taps, nu/levels out
- * of range), RLS_E_UNSUPPORTED (sparse operator, precision), RLS_E_OOM,
+ * of range), RLS_E_UNSUPPORTED (precision, boundary pair, a sparse
+ * operator with a precision other than RLS_PREC_MIXED_FP32 or rows or
+ * columns beyond the limits above, a blur band wider than a level or its
+ * LDS tile), RLS_E_OOM,
  * RLS_E_HIP. */
 rls_status rls_setup(rls_problem** out, const rls_op_desc* A,
                      const rls_grid_desc* g, const double* d, void* stream);
