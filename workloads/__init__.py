@@ -244,6 +244,29 @@ def config4() -> DeblurProblem:
                           "deblur2048_reflective_mixed")
 
 
+def paper_deblur(n: int = 64, noise: float = 0.01, nlam: int = 30,
+                 seed_cfg: int = 6) -> DeblurProblem:
+    """The deblurring problem of the paper's Section 4.6 on an n x n grid:
+    zero-boundary (Toeplitz) Kronecker blur with anisotropic truncated
+    Gaussians, radius 6 and sigma 1.25 n / 64 along the contiguous axis,
+    radius 7 and sigma 1.5 n / 64 across it, each normalized so that the
+    symmetric kernel sums to one; Neumann gradient; a seeded shapes phantom
+    (standing in for the paper's grains image); D = I, then 0.01 on phantom
+    edges; lambdas log-spaced in [1e-3, 1e2]; levels down to a 16 x 16
+    coarsest grid."""
+    x = shapes_phantom(n, n, 12, seed_for(seed_cfg, 0, 1))
+    tv = gaussian_taps(6, 1.25 * n / 64)
+    th = gaussian_taps(7, 1.5 * n / 64)
+    b = add_noise(blur_data(x, n, n, tv, th, BC_ZERO), noise,
+                  seed_for(seed_cfg, 0, 2))
+    ws = [edge_weights(x, n, n, L_NEUMANN, ell, "fixed", seed_for(seed_cfg))
+          for ell in range(2)]
+    levels = int(np.log2(n // 16)) + 1
+    return DeblurProblem(f"paper_deblur{n}", n, n, tv, th, BC_ZERO, L_NEUMANN,
+                         levels, x, b, lambda_grid(-3, 2, nlam), ws, 1e-8,
+                         noise)
+
+
 def small_deblur(nv: int, nh: int, r: int, sigma: float, bc: str, lbc: str,
                  levels: int, nlam: int = 4, seed_cfg: int = 9,
                  outer: int = 1, scheme: str = "uniform",

@@ -7,7 +7,9 @@ values, as the tomography configuration stores them) and handed to both.
 
 Geometry (unit pixels centred at the origin): pixel (i, j) of an N x N
 image, index p = i + N j, covers x in [j - N/2, j + 1 - N/2] and
-y in [i - N/2, i + 1 - N/2].  Angle k is theta_k = k pi / n_angles; bin b
+y in [i - N/2, i + 1 - N/2].  Angle k is theta_k = k pi / n_angles (full
+angle), or k times a given step (limited angle, e.g. 0, 2, ..., 130 degrees
+as in the paper's Section 4.5); bin b
 is the offset s_b = b - (n_bins - 1) / 2; ray (k, b) is the line
 x cos(theta) + y sin(theta) = s_b, row k * n_bins + b of A.  A[row, p] is
 the length of the ray inside pixel p.  A ray lying exactly on a grid line
@@ -38,15 +40,17 @@ def _axis_ray(N: int, s: float):
     return [k], [1.0]
 
 
-def parallel_beam(N: int, n_angles: int, n_bins: int):
+def parallel_beam(N: int, n_angles: int, n_bins: int,
+                  angle_step: float | None = None):
     """CSR arrays (rowptr int64, col int32, val float32) of the parallel-beam
     projector, m = n_angles * n_bins rows, N * N columns, columns sorted
-    within each row."""
+    within each row.  angle_step (radians): theta_k = k angle_step instead
+    of k pi / n_angles."""
     rows, cols, vals = [], [], []
     s = np.arange(n_bins) - (n_bins - 1) / 2.0
     edges = np.arange(N + 1) - N / 2.0
     for k in range(n_angles):
-        th = k * math.pi / n_angles
+        th = k * (math.pi / n_angles if angle_step is None else angle_step)
         c, sn = math.cos(th), math.sin(th)
         r0 = k * n_bins
         if abs(sn) < 1e-12 or abs(c) < 1e-12:
@@ -152,9 +156,10 @@ class CtProblem:
 
 def ct_problem(config: int, N: int, n_angles: int, n_bins: int | None,
                nellipses: int, noise: float, lams: np.ndarray, n_outer: int,
-               levels: int, name: str = "") -> CtProblem:
+               levels: int, name: str = "",
+               angle_step: float | None = None) -> CtProblem:
     nb = n_bins if n_bins is not None else math.ceil(N * math.sqrt(2.0))
-    rp, ci, va = parallel_beam(N, n_angles, nb)
+    rp, ci, va = parallel_beam(N, n_angles, nb, angle_step)
     x = ellipse_phantom(N, nellipses, seed_for(config, 0, 1))
     import scipy.sparse as sp
     A = sp.csr_matrix((va.astype(np.float64), ci, rp), shape=(n_angles * nb, N * N))
@@ -178,3 +183,14 @@ def small_ct(N: int = 32, n_angles: int = 24, levels: int = 3, nlam: int = 4,
     """A reduced tomography case with the same recipe (tests)."""
     return ct_problem(seed_cfg, N, n_angles, None, 4, 0.01,
                       lambda_grid(-3, 2, nlam), 2, levels, f"ct{N}_small")
+
+
+def limited_angle_ct(N: int = 64, noise: float = 0.01, nlam: int = 30,
+                     levels: int = 3, seed_cfg: int = 15) -> CtProblem:
+    """Limited-angle parallel beam as in the paper's Section 4.5: 66 angles
+    0, 2, ..., 130 degrees, ceil(N sqrt 2) bins, a seeded ellipse phantom
+    (standing in for the paper's grains image), D = I and 0.01 on phantom
+    edges, lambdas log-spaced in [1e-3, 1e2]."""
+    return ct_problem(seed_cfg, N, 66, None, 6, noise,
+                      lambda_grid(-3, 2, nlam), 2, levels,
+                      f"ct{N}_limited_angle", angle_step=math.pi / 90)
