@@ -148,3 +148,58 @@ def test_regularize_tomography_matches_oracle_algorithm():
     dref = np.ones(2 * n) if dw is None else dw
     assert np.abs(host(prob.weights()) - dref).max() <= 1e-6
     prob.close()
+
+
+def test_outer_argument_errors():
+    from paper_2306_11067_amd import RLSError
+    from paper_2306_11067_amd import _lib as L
+    P_ = W.small_deblur(64, 64, 3, 1.5, "reflective", "neumann", 3, nlam=12)
+    prob = _problem(64, 64, "neumann", "reflective", 3)
+    b = dev(P_.b)
+    bad = [
+        (P_.lams[:9], 2.0, 5),                      # fewer than 10 lambdas
+        (P_.lams[::-1], 2.0, 5),                    # decreasing
+        (np.r_[P_.lams[:5], P_.lams[4:11]], 2.0, 5),  # repeated value
+        (P_.lams, 0.0, 5),                          # q <= 0
+        (P_.lams, np.nan, 5),
+        (P_.lams, 2.0, 0),                          # no outer iteration
+    ]
+    for lams, q, mo in bad:
+        with pytest.raises(RLSError) as e:
+            prob.regularize(b, lams, q, 1e-10, maxouter=mo)
+        assert e.value.status == L.RLS_E_ARG, (lams, q, mo)
+    for q in (0.0, -1.0, np.inf):
+        with pytest.raises(RLSError) as e:
+            prob.update_weights(dev(P_.b), q)
+        assert e.value.status == L.RLS_E_ARG
+    # the problem is still usable after the rejected calls
+    assert np.array_equal(host(prob.weights()), np.ones(2 * 64 * 64))
+    prob.close()
+
+
+def test_regularize_one_outer_iteration_and_ten_lambdas():
+    # maxouter = 1: one full sweep, the corner of its own L-curve, no
+    # weight update; m = 10: every pruned window is the whole grid
+    from paper_2306_11067_amd import Problem, lcurve_corner
+    P_ = W.small_deblur(64, 64, 3, 1.5, "reflective", "neumann", 3, nlam=10)
+    prob = Problem(P_.nv, P_.nh, P_.taps_v, P_.taps_h, P_.bc, P_.lbc,
+                   P_.levels)
+    b = dev(P_.b)
+    x, chosen, info = prob.regularize(b, P_.lams, 2.0, 1e-12, maxouter=1)
+    assert info["outer"] == 1 and not info["stopped"]
+    assert np.array_equal(host(prob.weights()), np.ones(2 * P_.nv * P_.nh))
+    xs, res, sem, _ = prob.solve_sweep(b, P_.lams, 1e-12)
+    assert chosen == [lcurve_corner(P_.lams, res, sem)]
+    xr = host(xs[chosen[0]])
+    assert np.linalg.norm(host(x) - xr) <= 1e-12 * np.linalg.norm(xr)
+    n = P_.nv * P_.nh
+
+    def make(d):
+        return DeblurOracle(P_.nv, P_.nh, P_.taps_v, P_.taps_h, P_.bc, P_.lbc,
+                            np.ones(2 * n) if d is None else d, 1)
+
+    _, chosen_w, _, stopped_w = outer.regularize(
+        make, P_.b, P_.lams, 2.0, 6, P_.nv, P_.nh, P_.lbc)
+    _, chosen6, info6 = prob.regularize(b, P_.lams, 2.0, 1e-12, maxouter=6)
+    assert chosen6 == chosen_w and info6["stopped"] == stopped_w
+    prob.close()
