@@ -92,8 +92,9 @@ def traffic_per_launch(n, launches, nbytes):
     z = [p["slots"] for p in pts]
     slope = (t[-1] - t[0]) / (z[-1] - z[0])
     icpt = t[0] - slope * z[0]
-    # the timer's bytes are n (40 z + 16) summed over launches
-    slot_launches = (nbytes / n - 16.0 * launches) / 40.0
+    # the timer's bytes are n (32 z + 16) summed over launches (three-term
+    # form of the tiled FP64 step)
+    slot_launches = (nbytes / n - 16.0 * launches) / 32.0
     return (icpt * launches + slope * slot_launches) / launches
 
 

@@ -266,6 +266,7 @@ struct rls_problem {
     int hslots_n = 0;
     // live timing of the finest-level Chebyshev-step kernel
     bool timer_on = false;
+    bool fine_tiled = false;     // the last FP64 finest-level step was tiled
     struct TimedRun {
         hipEvent_t a = nullptr, b = nullptr;
         int launches = 0;
@@ -345,8 +346,13 @@ void smooth_fine(rls_problem* P, const ApplyArgs& a, hipStream_t s) {
         launch_ct_apply(PRO_PLAIN, EPI_CHEB, a, s);
         return;
     }
-    if (P->fine_generic) launch_apply(PRO_PLAIN, EPI_CHEB, a, s);
-    else launch_smooth_fine(with_fine_nt(P->fine_nt64, a), s);
+    if (P->fine_generic) {
+        launch_apply(PRO_PLAIN, EPI_CHEB, a, s);
+        P->fine_tiled = false;
+    } else {
+        P->fine_tiled = launch_smooth_fine_tiled(with_fine_nt(P->fine_nt64, a), s);
+        if (!P->fine_tiled) launch_apply(PRO_PLAIN, EPI_CHEB, a, s);
+    }
     if (P->timer_on) P->run_cur.launches += 1;
 }
 // FP32 and BF16 V-cycles: not timed (the kernel timer covers the FP64
@@ -949,6 +955,7 @@ void vcycle(rls_problem* P, int k, int nslot, const int* slots,
         c.in = bufs[cur];
         c.out = bufs[1 - cur];
         c.cheb = cheb + 2 * st;
+        c.fine_xstep = st - 2;
         if (top) smooth_fine(P, c, s);
         else level_apply(PRO_PLAIN, EPI_CHEB, c, s);
         cur = 1 - cur;
@@ -973,6 +980,7 @@ void vcycle(rls_problem* P, int k, int nslot, const int* slots,
             c.part_stride = ctl.dot_stride;
         }
         if (TIMED && top && st == 1) run_begin(P, s);
+        c.fine_xstep = st - 1;
         if (top && st > 0) smooth_fine(P, c, s);
         else level_apply(st == 0 ? PRO_PROLONG : PRO_PLAIN, EPI_CHEB, c, s);
         if (TIMED && top && st > 0 && st == nu - 1) run_end(P, s);
@@ -1875,7 +1883,9 @@ rls_status rls_solve_sweep(rls_problem* p, const double* b, const double* lam,
     if (p->timer_on) {
         drain_timer(p);
         // Every V-cycle of a slot takes part in 2 nu - 3 finest-level
-        // Chebyshev-step launches (40 bytes per pixel per slot); a launch
+        // Chebyshev-step launches (32 bytes per pixel per slot in the
+        // tiled kernel's three-term form: read x_k, x_{k-1} or d, f, write
+        // x_{k+1}; 40 in the general kernel, which also writes d); a launch
         // with at least one active slot also reads the two shared stencil
         // coupling planes (16 bytes per pixel; the centre coefficient is
         // minus their sum on the finest level).
@@ -1888,7 +1898,8 @@ rls_status rls_solve_sweep(rls_problem* p, const double* b, const double* lam,
             slot_launches += (double)hst[i].ncycle * per_cycle;
             max_cycles = std::max(max_cycles, hst[i].ncycle);
         }
-        p->timer_bytes += (double)n * 40.0 * slot_launches +
+        const double slot_bytes = p->fine_tiled ? 32.0 : 40.0;
+        p->timer_bytes += (double)n * slot_bytes * slot_launches +
                           (double)n * 16.0 * (double)max_cycles * per_cycle;
     }
     for (int i = 0; i < ns; ++i) {

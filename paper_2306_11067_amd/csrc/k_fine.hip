@@ -5,6 +5,10 @@
 //     d <- c1 d + c2 (f - K x) / diag(K),   x_out = x + d,
 // with K = G_h (x) G_v + lambda^2 S (paper Section 3.2: the separable Gram
 // of the blur plus the five-point stencil of L^T D^2 L on the fine grid).
+// In FP64 a run of these steps takes the equivalent three-term form
+//     x_{k+1} = x_k + c1 (x_k - x_{k-1}) + c2 (f - K x_k) / diag(K),
+// which reads x_k, x_{k-1} and f and writes x_{k+1} over x_{k-1} (32 bytes
+// per pixel instead of 40: d is never stored).
 //
 // It applies when both Gram bands of the level are uniform (one row of taps
 // plus a wrap or reflection index map), the stencil has five points and the
@@ -23,6 +27,8 @@
 //     so all four waves work, and its results stay in registers: the
 //     stencil term and the Chebyshev update follow directly, with 16-byte
 //     global loads and stores of the 4 rows.
+#include <type_traits>
+
 #include "common.h"
 
 namespace rls {
@@ -105,6 +111,9 @@ struct FineArgs {
     int nv, nh;
     int wrapv, wraph, per, f_shared;
     int cheb_stride, dot, part_stride;
+    // 0: read d, store d; 1: read d, store no d; 2: d = x_in - x_prev with
+    // x_prev read from out (overwritten in place by x_out), store no d
+    int xmode;
     int zslot[FZ];          // slot of grid z
     // half tap rows plus centre (the Gram rows are symmetric), padded to the
     // kernel's radius: entry k is the coefficient at offset k - BW
@@ -334,7 +343,8 @@ k_smooth_fine(FineArgs<R, V> a) {
     const int lane = t & 63;
     R pf[VWO], pd[VWO], psn[VWO], pse[VWO], psw[VWO], dgr[4];
     ldn(f, p0, pf);
-    ldn((const V*)dir, p0, pd);
+    // direction of the last step, or (three-term form) the previous iterate
+    ldn(a.xmode == 2 ? (const V*)out : (const V*)dir, p0, pd);
     ldn(a.sn, p0, psn);
     ldn(a.se, p0, pse);
     const R dgh = a.dh[gj];
@@ -487,13 +497,14 @@ k_smooth_fine(FineArgs<R, V> a) {
         sv = fma(psw[o], vc[o * S::SX - 1], sv);
         const R kvo = fma(l2, sv, kv[o]);
         const R dg = fma(dgl[r0 + o], dgh, l2 * sc);
-        nd[o] = fma(cd, pd[o], cr * (pf[o] - kvo) / dg);
+        const R dk = a.xmode == 2 ? v - pd[o] : pd[o];
+        nd[o] = fma(cd, dk, cr * (pf[o] - kvo) / dg);
         nx[o] = v + nd[o];
         // rounded product (never fused into the sum below: the lane that
         // adds it may not be the lane that formed it)
         prod[o] = __dmul_rn((double)pf[o], (double)nx[o]);
     }
-    stn(dir, p0, nd);
+    if (a.xmode == 0) stn(dir, p0, nd);
     stn(out, p0, nx);
     if (a.dot) {
         // Partial of f . x_out over the tile in one order for both thread
@@ -579,6 +590,11 @@ FineArgs<R, V> fine_args(const ApplyArgsT<R, V>& a, int bw) {
     f.cheb_stride = a.cheb_stride;
     f.dot = a.dot;
     f.part_stride = a.part_stride;
+    // the three-term form only where x is stored in FP64: in FP32 or BF16
+    // the difference of two stored iterates would lose the direction
+    constexpr bool xform =
+        std::is_same<R, double>::value && std::is_same<V, double>::value;
+    f.xmode = xform && a.fine_xstep >= 0 ? (a.fine_xstep == 0 ? 1 : 2) : 0;
     for (int i = 0; i < FZ; ++i)
         f.zslot[i] = i < a.zn ? a.zslot[i] : i < a.nslot ? i : 0;
     return f;
