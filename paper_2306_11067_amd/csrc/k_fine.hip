@@ -5,7 +5,7 @@
 //     d <- c1 d + c2 (f - K x) / diag(K),   x_out = x + d,
 // with K = G_h (x) G_v + lambda^2 S (paper Section 3.2: the separable Gram
 // of the blur plus the five-point stencil of L^T D^2 L on the fine grid).
-// In FP64 a run of these steps takes the equivalent three-term form
+// In FP64 and FP32 a run of these steps takes the equivalent three-term form
 //     x_{k+1} = x_k + c1 (x_k - x_{k-1}) + c2 (f - K x_k) / diag(K),
 // which reads x_k, x_{k-1} and f and writes x_{k+1} over x_{k-1} (32 bytes
 // per pixel instead of 40: d is never stored).
@@ -590,10 +590,11 @@ FineArgs<R, V> fine_args(const ApplyArgsT<R, V>& a, int bw) {
     f.cheb_stride = a.cheb_stride;
     f.dot = a.dot;
     f.part_stride = a.part_stride;
-    // the three-term form only where x is stored in FP64: in FP32 or BF16
-    // the difference of two stored iterates would lose the direction
-    constexpr bool xform =
-        std::is_same<R, double>::value && std::is_same<V, double>::value;
+    // the three-term form where x is stored in the arithmetic type (FP64,
+    // FP32): forming the direction from two stored iterates then adds
+    // rounding of the size each stored iterate already carries.  BF16
+    // vectors keep the stored direction.
+    constexpr bool xform = std::is_same<R, V>::value;
     f.xmode = xform && a.fine_xstep >= 0 ? (a.fine_xstep == 0 ? 1 : 2) : 0;
     for (int i = 0; i < FZ; ++i)
         f.zslot[i] = i < a.zn ? a.zslot[i] : i < a.nslot ? i : 0;

@@ -206,7 +206,7 @@ struct ApplyArgsT {
     // threads per workgroup of the tiled finest-level Chebyshev kernel
     // (256 or 512, both giving the same results; 0: built-in rule)
     int fine_nt = 0;
-    // position of this step in a run of consecutive tiled FP64 steps (-1:
+    // position of this step in a run of consecutive tiled steps (-1:
     // not in such a run).  Those steps use the three-term form of the
     // recurrence: the first reads the direction d the previous (general)
     // step stored, the others form it as x_k - x_{k-1} from the output
