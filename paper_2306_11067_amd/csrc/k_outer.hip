@@ -5,9 +5,9 @@
 // Weight update: with w = |D L x| over both gradient planes (vertical
 // differences first, then horizontal, each plane indexed like the image),
 //     g = w / ||w||_inf,   d = 1 - g^q,   D <- diag(d) D.
-// Two passes over the 2n gradient entries: per-block maxima, then every
-// block reduces the (at most WMAX_BLOCKS) maxima itself and writes the new
-// weights.  The maximum is exact, so the result does not depend on the
+// Two passes over the 2n gradient entries, each on at most WMAX_BLOCKS
+// grid-stride blocks: per-block maxima, then every block reduces the
+// maxima itself and writes the new weights.  The maximum is exact, so the result does not depend on the
 // launch shape.  ||w||_inf = 0 leaves D unchanged (g = 0).
 #include <algorithm>
 #include <cmath>
@@ -141,8 +141,9 @@ void launch_weight_update(const double* x, const double* d, int nv, int nh,
     const int nb = (int)std::min<int64_t>((ne + WT - 1) / WT, WMAX_BLOCKS);
     hipLaunchKernelGGL(k_weight_max, dim3(nb), dim3(WT), 0, s, x, d, nv, nh,
                        periodic, part);
-    const int nu = (int)std::min<int64_t>((ne + WT - 1) / WT, 65535);
-    hipLaunchKernelGGL(k_weight_update, dim3(nu), dim3(WT), 0, s, x, d, nv, nh,
+    // every block of the update pass reads the nb maxima first: the same
+    // cap keeps that re-read small against the 40 bytes per entry it moves
+    hipLaunchKernelGGL(k_weight_update, dim3(nb), dim3(WT), 0, s, x, d, nv, nh,
                        periodic, q, part, nb, dout, top);
 }
 
