@@ -196,3 +196,55 @@ class VCycle:
         return chebyshev(K, self.dinv[k], b, x, lo, hi, self.nu[k])
 
     __call__ = cycle
+
+
+def cg_relax(K, dinv, b, x, steps: int):
+    """`steps` iterations of CG preconditioned by diag^-1 on K x = b from x
+    (None for zero): the relaxation of the paper's Section 3.2 (diagonally
+    preconditioned CG on every level, restarted at each relaxation)."""
+    x = np.zeros_like(b) if x is None else np.array(x, dtype=np.float64)
+    r = b - K(x)
+    z = dinv * r
+    p = z.copy()
+    gamma = float(r @ z)
+    for i in range(steps):
+        if gamma == 0.0:
+            break
+        q = K(p)
+        alpha = gamma / float(p @ q)
+        x = x + alpha * p
+        r = r - alpha * q
+        if i + 1 < steps:
+            z = dinv * r
+            gnew = float(r @ z)
+            p = z + (gnew / gamma) * p
+            gamma = gnew
+    return x
+
+
+class KrylovVCycle:
+    """z ~ M^{-1} r by one V(nu_pre, nu_post) cycle whose relaxation on every
+    level but the coarsest is diagonally preconditioned CG (Section 3.2: two
+    pre- and one post-relaxation sweep, one CG iteration per sweep), with
+    the exact coarsest solve of Algorithm 1.  The CG coefficients depend on
+    the residual, so the cycle is not a fixed linear map: it belongs under
+    a flexible outer method (the paper uses FGMRES)."""
+
+    def __init__(self, H: Hierarchy, lam: float, nu_pre=2, nu_post=1):
+        self.H, self.lam = H, lam
+        self.nu_pre, self.nu_post = nu_pre, nu_post
+        self.dinv = [1.0 / H.diag(k, lam) for k in range(H.levels)]
+        self.chol = sla.cho_factor(H.coarse_matrix(lam), lower=True)
+
+    def cycle(self, b, k: int = 0):
+        H, lam = self.H, self.lam
+        if k == H.levels - 1:
+            return sla.cho_solve(self.chol, b)
+        K = lambda v: H.K(k, lam, v)
+        x = cg_relax(K, self.dinv[k], b, None, self.nu_pre)
+        res = b - K(x)
+        e = self.cycle(H.P[k].T @ res, k + 1)
+        x = x + H.P[k] @ e
+        return cg_relax(K, self.dinv[k], b, x, self.nu_post)
+
+    __call__ = cycle

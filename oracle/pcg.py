@@ -11,7 +11,7 @@ import numpy as np
 
 from . import direct
 from . import operators as ops
-from .multigrid import Hierarchy, SparseOp, VCycle
+from .multigrid import Hierarchy, KrylovVCycle, SparseOp, VCycle
 
 
 def pcg(K, f, M=None, x0=None, tol=1e-8, maxit=10000, absolute=False,
@@ -135,6 +135,15 @@ class DeblurOracle:
         V = self.vcycle(lam, nu, ratio)
         return pcg(self.K(lam), self.rhs(b), V, x0=x0, tol=tol, maxit=maxit,
                    absolute=absolute)
+
+    def krylov_mg_pcg(self, b, lam, tol=1e-8, nu_pre=2, nu_post=1, x0=None,
+                      maxit=10000, absolute=False):
+        """Flexible PCG preconditioned by the V(nu_pre, nu_post) cycle with
+        diagonally preconditioned CG relaxation (the paper's preconditioner,
+        Section 3.2; the paper runs it under FGMRES)."""
+        V = KrylovVCycle(self.H, lam, nu_pre, nu_post)
+        return pcg(self.K(lam), self.rhs(b), V, x0=x0, tol=tol, maxit=maxit,
+                   absolute=absolute, flexible=True)
 
 
 class CtOracle(DeblurOracle):
