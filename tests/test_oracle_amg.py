@@ -95,3 +95,20 @@ def test_amg_cycles_reduce_the_energy_error_and_precondition_pcg():
         Vc = VCycle(H, lam, nu=2, ratio=4.0)
         x, its, _, _ = pcg(K, O.rhs(P.b), Vc, tol=1e-11, maxit=20000)
         assert np.linalg.norm(x - xr) <= 1e-7 * np.linalg.norm(xr), (lam, its)
+
+
+def test_amg_hierarchy_on_a_tomography_operator():
+    # the hierarchy only needs A explicitly: the same construction serves a
+    # sparse projector (one-sided A_{k+1} = A_k P_k)
+    from oracle.pcg import CtOracle
+    from workloads.ct import small_ct
+    C = small_ct(32, 24, 3, 3)
+    O = CtOracle(C.matrix(), C.N, C.lbc, C.weights[1], 1)
+    H = AmgHierarchy(O.A, O.M, levels=4, max_coarse=200)
+    assert H.levels >= 3
+    for lam in (1e-2, 1.0):
+        K = O.K(lam)
+        xr, _ = O.reference(C.b, lam)
+        x, its, _, _ = pcg(K, O.rhs(C.b), VCycle(H, lam, nu=2, ratio=4.0),
+                           tol=1e-12, maxit=20000)
+        assert np.linalg.norm(x - xr) <= 1e-7 * np.linalg.norm(xr), (lam, its)
