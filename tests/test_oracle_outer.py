@@ -37,6 +37,21 @@ def test_weights_two_step_image_by_hand():
     assert np.array_equal(dn, want)
 
 
+def test_weights_use_the_current_weights_in_g():
+    # the same image with D = 0.5 on the jump between columns 0 and 1:
+    # |D L x| is 0.5 on both jumps, so g = 1 on both and both get d = 0
+    # (g taken from |L x| alone would give 0.75 on the second jump)
+    nv, nh = 4, 3
+    x = np.repeat([0.0, 1.0, 1.5], nv)
+    d0 = np.ones(2 * nv * nh)
+    d0[nv * nh + 0:nv * nh + 4] = 0.5
+    dn, top = outer.weight_update(d0, x, nv, nh, "neumann", 2.0)
+    assert top == 0.5
+    want = np.ones(2 * nv * nh)
+    want[nv * nh + 0:nv * nh + 8] = 0.0
+    assert np.array_equal(dn, want)
+
+
 def test_weights_periodic_wrap_jump_is_largest():
     # a ramp 0..5 along the contiguous axis, periodic: the wrap-around
     # difference (0 - 5) is the largest, so only the last row gets d = 0
