@@ -315,6 +315,30 @@ def test_chebyshev_polynomial():
         np.testing.assert_allclose(x, want, atol=1e-14)
 
 
+def test_three_term_chebyshev_form_has_the_same_polynomial():
+    # The tiled smoothing kernel runs the recurrence in three-term form,
+    # x_{k+1} = x_k + c1 (x_k - x_{k-1}) + c2 D^-1 (b - K x_k), with the
+    # two-term coefficients c1 = rho_k rho_{k-1}, c2 = 2 rho_k / delta and
+    # the first step x_1 = x_0 + D^-1 r_0 / theta.  Its error propagation
+    # must be the same Chebyshev ratio T_s((theta - mu)/delta) / T_s(theta/delta).
+    mu = np.linspace(0.05, 2.0, 40)
+    a, b = 0.4, 2.0
+    theta, delta = (a + b) / 2, (b - a) / 2
+    sigma = theta / delta
+    for steps in (1, 2, 3, 4, 6):
+        x_prev = np.ones_like(mu)                  # x_0: error e0 = 1
+        x = x_prev + (-mu * x_prev) / theta        # b = 0, D = I
+        rho_old = 1.0 / sigma
+        for _ in range(1, steps):
+            rho = 1.0 / (2.0 * sigma - rho_old)
+            c1, c2 = rho * rho_old, 2.0 * rho / delta
+            x, x_prev = x + c1 * (x - x_prev) + c2 * (-mu * x), x
+            rho_old = rho
+        want = eval_chebyt(steps, (theta - mu) / delta) / \
+            eval_chebyt(steps, theta / delta)
+        np.testing.assert_allclose(x, want, atol=1e-14)
+
+
 def test_coarse_correction_is_projection():
     O = _small_oracle(levels=2)
     H = O.H
