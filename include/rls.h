@@ -280,11 +280,13 @@ rls_status rls_gershgorin(rls_problem* p, int level, const double* lam,
  * on the launch stream.
  * rls_kernel_timer(p, 1) enables and resets, (p, 0) disables.
  * rls_kernel_timer_read returns the number of timed launches, their summed
- * duration in seconds and their summed algorithmic bytes: per pixel, 40
- * bytes per active lambda (read x, f, d; write x, d) plus, for launches with
- * an active lambda, 16 bytes of shared stencil couplings (north and east;
- * the centre is minus the sum of the four couplings), every array counted
- * once. */
+ * duration in seconds and their summed algorithmic bytes: per pixel, 32
+ * bytes per active lambda for the tiled kernel, which runs the three-term
+ * form of the recurrence (read x_k, x_{k-1} or the first step's direction,
+ * f; write x_{k+1}), or 40 for the general kernel (read x, f, d; write x,
+ * d), plus, for launches with an active lambda, 16 bytes of shared stencil
+ * couplings (north and east; the centre is minus the sum of the four
+ * couplings), every array counted once. */
 rls_status rls_kernel_timer(rls_problem* p, int enable);
 rls_status rls_kernel_timer_read(const rls_problem* p, long long* launches,
                                  double* seconds, double* bytes);

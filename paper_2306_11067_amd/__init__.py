@@ -24,6 +24,9 @@ PREC = {"fp64": L.RLS_PREC_FP64, "mixed_fp32": L.RLS_PREC_MIXED_FP32,
 
 
 class RLSError(RuntimeError):
+    """A failed library call: `status` is the RLS_E_* code, the message the
+    library's own description of the failure."""
+
     def __init__(self, status: int, msg: str):
         super().__init__(f"{L.STATUS_NAMES.get(status, status)}: {msg}")
         self.status = status
@@ -83,6 +86,7 @@ class Problem:
         self.m = self.n          # data values (A is square for the blur)
 
     def close(self):
+        """Free the problem's device memory (idempotent)."""
         if getattr(self, "_h", None):
             self._lib.rls_destroy(self._h)
             self._h = None
@@ -95,11 +99,27 @@ class Problem:
 
     # ------------------------------------------------------------ main ABI
     def set_weights(self, weights=None):
+        """Install the weights D of a new outer iteration (2n FP64 values on
+        the device, vertical-difference plane first; None for D = I) and
+        rebuild the coarse stencils of L^T D^2 L (paper Section 3.2)."""
         d = None if weights is None else _dptr(weights, "weights", 2 * self.n)
         _check(self._lib.rls_set_weights(self._h, d, _stream()))
 
     def solve_sweep(self, b, lams, tol, x0=None, x=None, maxit=100000,
                     tol_mode="relative", poll_every=32, graph=True):
+        """Solve (A^T A + lambda^2 L^T D^2 L) x = A^T b for every lambda at
+        once (batched PCG with the multigrid V-cycle).
+
+        b: device FP64 data (m values); lams: the lambdas (> 0, any order);
+        tol: residual target, relative to ||A^T b|| or absolute
+        (tol_mode); x0: optional device warm starts, len(lams) * n values;
+        x: optional output buffer (may be x0).  poll_every: iterations
+        between host convergence checks; graph: replay iteration chunks as
+        HIP graphs (same results either way).
+
+        Returns (x viewed as (len(lams), n), ||A x - b|| per lambda,
+        ||D L x|| per lambda, per-lambda dicts with iters, flags, relres
+        (recursive) and relres_true (recomputed in FP64))."""
         import torch
         lam, plam = _dbl(lams)
         nl = len(lam)
@@ -131,6 +151,7 @@ class Problem:
         return top.value
 
     def weights(self):
+        """The current weights D (2n FP64 values on the device)."""
         import torch
         out = torch.empty(2 * self.n, dtype=torch.float64, device="cuda")
         _check(self._lib.rls_get_weights(self._h, _dptr(out, "d"), _stream()))
@@ -157,11 +178,14 @@ class Problem:
 
     # ------------------------------------------------------------ step ABI
     def level_shape(self, level):
+        """(nv, nh) of a multigrid level (0 is the finest)."""
         a, b = C.c_int(), C.c_int()
         _check(self._lib.rls_level_shape(self._h, level, C.byref(a), C.byref(b)))
         return a.value, b.value
 
     def apply_normal(self, level, lams, v):
+        """K_k(lambda) v on a level for each lambda (v: device, one vector
+        of the level per lambda, concatenated)."""
         import torch
         lam, plam = _dbl(lams)
         nv, nh = self.level_shape(level)
@@ -173,6 +197,8 @@ class Problem:
         return out
 
     def vcycle(self, lams, r):
+        """One V-cycle z = M^{-1} r per lambda (paper Algorithm 1), with the
+        problem's smoothing settings and precision."""
         import torch
         lam, plam = _dbl(lams)
         z = torch.empty_like(r)
@@ -182,6 +208,7 @@ class Problem:
         return z
 
     def stencil(self, level):
+        """The level's stencil planes of L^T D^2 L (5 x n_k, host copy)."""
         nv, nh = self.level_shape(level)
         out = np.zeros(5 * nv * nh)
         _check(self._lib.rls_get_stencil(
@@ -189,6 +216,8 @@ class Problem:
         return out.reshape(5, nv * nh)
 
     def gram_band(self, level, direction):
+        """The level's 1D Gram band of the blur in one direction (0: along
+        the contiguous axis, 1: across it), host copy."""
         bw = C.c_int()
         _check(self._lib.rls_get_gram_band(self._h, level, direction,
                                            C.byref(bw), None))
@@ -201,6 +230,8 @@ class Problem:
         return out.reshape(n, 2 * bw.value + 1)
 
     def gershgorin(self, level, lams):
+        """Gershgorin bound of diag(K_k)^-1 K_k per lambda (the top of the
+        Chebyshev smoothing interval)."""
         lam, plam = _dbl(lams)
         rho = np.zeros(len(lam))
         _check(self._lib.rls_gershgorin(
@@ -209,15 +240,19 @@ class Problem:
         return rho
 
     def kernel_timer(self, enable=True):
+        """Time the FP64 finest-level smoothing launches (HIP events around
+        each run of consecutive launches; graphs are off while it is on)."""
         _check(self._lib.rls_kernel_timer(self._h, 1 if enable else 0))
 
     def kernel_timer_read(self):
+        """(launches, seconds, algorithmic bytes) since the timer was enabled."""
         n, sec, byt = C.c_longlong(), C.c_double(), C.c_double()
         _check(self._lib.rls_kernel_timer_read(self._h, C.byref(n),
                                                C.byref(sec), C.byref(byt)))
         return n.value, sec.value, byt.value
 
     def forward(self, x, nvec=1):
+        """y = A x for nvec vectors on the device."""
         import torch
         y = torch.empty(nvec * self.m, dtype=torch.float64, device=x.device)
         _check(self._lib.rls_apply_forward(self._h, _dptr(x, "x", nvec * self.n),
@@ -225,6 +260,7 @@ class Problem:
         return y
 
     def adjoint(self, y, nvec=1):
+        """x = A^T y for nvec vectors on the device."""
         import torch
         x = torch.empty(nvec * self.n, dtype=torch.float64, device=y.device)
         _check(self._lib.rls_apply_adjoint(self._h, _dptr(y, "y", nvec * self.m),
